@@ -1,0 +1,218 @@
+/*
+ * mk_tfhe.h - C ABI of the MI355X (gfx950) multi-key TFHE gate-bootstrapping
+ * library.
+ *
+ * The operations follow the paper's statement of the problem (Jiang et al.,
+ * "Privacy-Preserving Distributed Machine Learning Made Faster"):
+ *   §3.2  MKTFHE.Setup / KeyGen / SymEnc / SymDec / MKKeySwitch / NAND,
+ *   §4.1  the bootstrapped AND/OR/NOR/XOR/XNOR gates, Eqs. (6)-(11), and the
+ *         free NOT, Eq. (8),
+ *   §4.3-§4.5  k-bit two's-complement adder, multiplier, subtractor and
+ *         divider (Algs. 3-6), evaluated as layered gate netlists.
+ * The scheme's internals, which the paper does not print, follow the
+ * MKTFHE scheme it builds on (Chen, Chillotti, Song 2019): uni-encryption
+ * bootstrapping keys, hybrid-product blind rotation, sample extraction and
+ * per-party key switching.
+ *
+ * Conventions
+ *   Torus32   a torus value x in [0,1) is the uint32_t round(x * 2^32).
+ *   LWE ciphertext of k parties: words (b, a_1[0..n), ..., a_k[0..n)),
+ *             kn+1 words, phase b + sum_i <a_i, s_i>; bit m is encoded as
+ *             phase m/4.  Arrays of ciphertexts have a row stride of
+ *             `stride` words (stride >= kn+1).
+ *   Ownership the context owns all key material (host and device) and its
+ *             device scratch; the caller owns every ciphertext buffer.
+ *   Streams   device entry points are asynchronous on the given hipStream_t
+ *             (passed as void*, NULL = default stream); host entry points are
+ *             synchronous.
+ *   Errors    0 on success, a negative MK_E* code otherwise; no exception
+ *             crosses the ABI.  mk_last_error() returns a thread-local message
+ *             describing the most recent failure on the calling thread.
+ */
+#ifndef MK_TFHE_H
+#define MK_TFHE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ----------------------------------------------------------- codes ---- */
+#define MK_OK 0
+#define MK_EINVAL -1   /* bad argument (null pointer, range, size)        */
+#define MK_ENOMEM -2   /* host or device allocation failed                */
+#define MK_EDEVICE -3  /* a HIP call or kernel launch failed              */
+#define MK_ESTATE -4   /* keys missing / evaluation key not uploaded      */
+#define MK_EPARAM -5   /* parameters unsupported (see mk_setup)           */
+
+/* Gate types.  NAND..XNOR are bootstrapped (§4.1); NOT is free (Eq. (8)). */
+#define MK_GATE_NAND 0
+#define MK_GATE_AND 1
+#define MK_GATE_OR 2
+#define MK_GATE_NOR 3
+#define MK_GATE_XOR 4
+#define MK_GATE_XNOR 5
+#define MK_GATE_NOT 6
+
+/* Blind-rotation implementations (bit-identical results). */
+#define MK_PATH_I32 0     /* exact 32-bit integer VALU products            */
+#define MK_PATH_MFMA_I8 1 /* exact split-limb int8 MFMA products           */
+
+/* ------------------------------------------------------- parameters ---- */
+/*
+ * Parameter set (symbols of Table 7 plus the party count k of §3.1).
+ *   k              parties, 1..8
+ *   n              LWE dimension
+ *   N              ring dimension, a power of two in [16, 4096]
+ *   bk_log_base    log2 of the gadget base B (must be 8: digits are int8)
+ *   bk_ell         gadget length, with bk_log_base*bk_ell <= 30
+ *   ks_log_base    log2 of the key-switching base B' (1..4)
+ *   ks_t           key-switching digits, ks_log_base*ks_t <= 30
+ *   *_noise_log2   noise standard deviation 2^-s in torus units for the
+ *                  public/bootstrapping keys, key-switching keys and fresh
+ *                  encryptions (1 <= s <= 40)
+ * mk_setup rejects with MK_EPARAM sets for which the int8 contraction could
+ * overflow its int32 accumulators: (k+1)*bk_ell*N*2^14 must be < 2^31.
+ */
+typedef struct mk_params {
+    int32_t k, n, N;
+    int32_t bk_log_base, bk_ell;
+    int32_t ks_log_base, ks_t;
+    int32_t bk_noise_log2, ks_noise_log2, lwe_noise_log2;
+} mk_params;
+
+typedef struct mk_ctx mk_ctx;
+
+/* Circuit netlist for mk_eval_circuit (Algs. 3-6 are such netlists).
+ * Wires 0 and 1 are the constants 0 and 1 (noiseless trivial ciphertexts);
+ * wires 2..n_wires-1 are inputs or gate outputs.  Gates must be in
+ * topological order; a gate of type MK_GATE_NOT ignores in2. */
+typedef struct mk_gate {
+    int32_t type, in1, in2, out;
+} mk_gate;
+
+typedef struct mk_circuit {
+    int32_t n_wires;
+    int32_t n_inputs;
+    const int32_t *inputs;   /* wire id of each input                     */
+    int32_t n_outputs;
+    const int32_t *outputs;  /* wire id of each output                    */
+    int32_t n_gates;
+    const mk_gate *gates;
+} mk_circuit;
+
+/* ------------------------------------------------ setup and keys (host) -- */
+
+/* §3.2 MKTFHE.Setup: validate `p` and sample the common reference string
+ * a in T_N[X]^bk_ell from `seed`.  *out receives a new context (free it with
+ * mk_free).  Errors: MK_EINVAL (null), MK_EPARAM (unsupported parameters),
+ * MK_ENOMEM. */
+int mk_setup(const mk_params *p, uint64_t seed, mk_ctx **out);
+
+/* §3.2 MKTFHE.KeyGen for party `party` (0..k-1): LWE key s, ring key z,
+ * public key pk = -z*a + e, bootstrapping key (a uni-encryption of every bit
+ * of s under z), and key-switching key from z to s, all derived from `seed`
+ * by the library's Philox4x64-10 streams.  Host only.  Errors: MK_EINVAL. */
+int mk_keygen(mk_ctx *ctx, int party, uint64_t seed);
+
+/* Serialise the keys of `party` (or the CRS with party = -1) into `buf`.
+ * With buf == NULL only *len is set to the required size.  Layout (little
+ * endian): "MKK1", int32 version=1, the 10 int32 of mk_params, int32 party,
+ * then for party -1: crs u32[ell][N]; for a party: s u8[n], z u8[N],
+ * pk u32[ell][N], bk u32[n][3][ell][N] (components d, f0, f1),
+ * ks u32[N][t][B'-1][n+1] (rows (b, a)).  Errors: MK_EINVAL, MK_ESTATE. */
+int mk_export_keys(const mk_ctx *ctx, int party, void *buf, size_t *len);
+
+/* Load keys written by mk_export_keys (same parameters required).  Errors:
+ * MK_EINVAL (size, magic or parameter mismatch). */
+int mk_import_keys(mk_ctx *ctx, int party, const void *buf, size_t len);
+
+/* The server-side "reconstruction" of the parties' keys into the evaluation
+ * key (Alg. 7/8 step 1): copies the bootstrapping keys, the public keys
+ * (as b_0 = -a, b_1..b_k) and the key-switching keys to the current HIP
+ * device, in the layouts of both blind-rotation paths.  Synchronous on
+ * `stream`.  Errors: MK_ESTATE (a party has no keys), MK_ENOMEM, MK_EDEVICE. */
+int mk_upload_eval_key(mk_ctx *ctx, void *stream);
+
+/* §3.2 MKTFHE.SymEnc by `party` of `count` bits (0/1), extended to k slots
+ * (the other parties' slots are zero).  Randomness comes from `seed`
+ * (message j uses stream index j).  out_host: count rows of stride_words
+ * words (host memory).  Errors: MK_EINVAL, MK_ESTATE. */
+int mk_encrypt(const mk_ctx *ctx, int party, const uint8_t *bits, size_t count,
+               uint64_t seed, uint32_t *out_host, size_t stride_words);
+
+/* §3.2 MKTFHE.SymDec with every party's secret key: bit = 1 iff the phase
+ * is in [1/8, 5/8).  ct_host: host rows.  Errors: MK_EINVAL, MK_ESTATE. */
+int mk_decrypt(const mk_ctx *ctx, const uint32_t *ct_host, size_t count,
+               size_t stride_words, uint8_t *bits);
+
+/* Noiseless ciphertexts of `bits` (b = bit/4, a = 0), host memory. */
+int mk_trivial(const mk_ctx *ctx, const uint8_t *bits, size_t count,
+               uint32_t *out_host, size_t stride_words);
+
+/* ------------------------------------------------- device entry points -- */
+
+/* MKNOT, Eq. (8): out = (0, 1/4) - in for `count` device rows; no
+ * bootstrapping.  in/out may alias.  Errors: MK_EINVAL, MK_EDEVICE. */
+int mk_not(const mk_ctx *ctx, const uint32_t *in_dev, uint32_t *out_dev,
+           size_t count, size_t stride, void *stream);
+
+/* Bootstrapped gates of §4.1 (Eqs. (6)-(11)) on `count` independent pairs:
+ * out[g] = Boots_{types[g]}(in1[g], in2[g]).  All pointers are device
+ * memory; rows have `stride` words.  Pipeline: pre-combination and modulus
+ * switch, blind rotation (path MK_PATH_I32 or MK_PATH_MFMA_I8, identical
+ * bits), sample extraction, multi-key key switching.  `out` must not alias
+ * the inputs.  Errors: MK_EINVAL (type >= MK_GATE_NOT, sizes),
+ * MK_ESTATE (mk_upload_eval_key not called), MK_ENOMEM, MK_EDEVICE. */
+int mk_bootstrap_gate(mk_ctx *ctx, const uint8_t *gate_types_dev,
+                      const uint32_t *in1_dev, const uint32_t *in2_dev,
+                      uint32_t *out_dev, size_t count, size_t stride, int path,
+                      void *stream);
+
+/* Evaluates `batch` independent instances of a netlist (Algs. 3-6).
+ * in_dev: [n_inputs][batch][stride] words, out_dev: [n_outputs][batch]
+ * [stride] words.  The netlist is levelled by bootstrapping depth; NOT
+ * gates are folded into their consumers; every level runs as one batch of
+ * all its gates over all instances.  Errors as mk_bootstrap_gate, plus
+ * MK_EINVAL for a malformed netlist. */
+int mk_eval_circuit(mk_ctx *ctx, const mk_circuit *c, const uint32_t *in_dev,
+                    uint32_t *out_dev, size_t batch, size_t stride, int path,
+                    void *stream);
+
+/* Stage entry points (the same kernels as mk_bootstrap_gate, exposed so that
+ * each step can be checked on its own).
+ *   mk_blind_rotate: abar_dev holds `count` rows of kn+1 uint32 values in
+ *     [0, 2N) (modulus-switched b, a_1..a_k); acc_dev receives count rows of
+ *     (k+1)*N words (the RLWE accumulator c_0..c_k) after the first
+ *     `max_steps` CMux steps (all k*n when max_steps < 0).
+ *   mk_extract_keyswitch: acc_dev rows of (k+1)*N words -> out_dev LWE rows
+ *     (sample extraction, + 1/8, key switching). */
+int mk_blind_rotate(mk_ctx *ctx, const uint32_t *abar_dev, uint32_t *acc_dev,
+                    size_t count, int max_steps, int path, void *stream);
+int mk_extract_keyswitch(mk_ctx *ctx, const uint32_t *acc_dev,
+                         uint32_t *out_dev, size_t count, size_t stride,
+                         void *stream);
+
+/* Netlist builders (§4.3-§4.5).  Each writes into caller-provided arrays
+ * sized by a first call with gates == NULL (which only sets *n_gates and
+ * *n_wires).  Input wires: operand a bits (LSB first) then operand b bits;
+ * output wires: result bits LSB first.
+ *   op: 0 adder (k-bit, 5k gates), 1 subtractor (6k gates),
+ *       2 multiplier (k x k -> 2k bits, signed), 3 divider (k-bit signed
+ *       truncating quotient then remainder, 2k outputs). */
+int mk_build_operator(int op, int kbits, mk_gate *gates, int32_t *n_gates,
+                      int32_t *n_wires, int32_t *inputs, int32_t *outputs);
+
+/* Thread-local description of the last error on this thread. */
+const char *mk_last_error(void);
+
+/* Releases the context, its host keys and device memory. */
+void mk_free(mk_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MK_TFHE_H */

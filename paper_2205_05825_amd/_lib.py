@@ -1,0 +1,249 @@
+"""ctypes binding of libmktfhe.so (the C ABI declared in include/mk_tfhe.h).
+
+Argument marshalling only: every step of the bootstrapping runs inside the
+library's HIP kernels.  Device buffers are torch tensors on the current
+HIP device (``tensor.data_ptr()``); host buffers are numpy arrays.  If the
+library has not been built, importing this module raises ImportError: there
+is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmktfhe.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        "libmktfhe.so is not built; run `python -m paper_2205_05825_amd.build` "
+        "(hipcc, gfx950) first")
+
+_L = ctypes.CDLL(LIB_PATH)
+
+MK_OK, MK_EINVAL, MK_ENOMEM, MK_EDEVICE, MK_ESTATE, MK_EPARAM = 0, -1, -2, -3, -4, -5
+PATH_I32, PATH_MFMA_I8 = 0, 1
+NAND, AND, OR, NOR, XOR, XNOR, NOT = 0, 1, 2, 3, 4, 5, 6
+
+
+class MkParams(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int32) for name in (
+        "k", "n", "N", "bk_log_base", "bk_ell", "ks_log_base", "ks_t",
+        "bk_noise_log2", "ks_noise_log2", "lwe_noise_log2")]
+
+
+class MkGate(ctypes.Structure):
+    _fields_ = [("type", ctypes.c_int32), ("in1", ctypes.c_int32),
+                ("in2", ctypes.c_int32), ("out", ctypes.c_int32)]
+
+
+class MkCircuit(ctypes.Structure):
+    _fields_ = [("n_wires", ctypes.c_int32),
+                ("n_inputs", ctypes.c_int32), ("inputs", ctypes.POINTER(ctypes.c_int32)),
+                ("n_outputs", ctypes.c_int32), ("outputs", ctypes.POINTER(ctypes.c_int32)),
+                ("n_gates", ctypes.c_int32), ("gates", ctypes.POINTER(MkGate))]
+
+
+_vp, _sz, _i, _u64 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_uint64
+_SIGS = {
+    "mk_setup": ([ctypes.POINTER(MkParams), _u64, ctypes.POINTER(_vp)], _i),
+    "mk_keygen": ([_vp, _i, _u64], _i),
+    "mk_export_keys": ([_vp, _i, _vp, ctypes.POINTER(_sz)], _i),
+    "mk_import_keys": ([_vp, _i, _vp, _sz], _i),
+    "mk_upload_eval_key": ([_vp, _vp], _i),
+    "mk_encrypt": ([_vp, _i, _vp, _sz, _u64, _vp, _sz], _i),
+    "mk_decrypt": ([_vp, _vp, _sz, _sz, _vp], _i),
+    "mk_trivial": ([_vp, _vp, _sz, _vp, _sz], _i),
+    "mk_not": ([_vp, _vp, _vp, _sz, _sz, _vp], _i),
+    "mk_bootstrap_gate": ([_vp, _vp, _vp, _vp, _vp, _sz, _sz, _i, _vp], _i),
+    "mk_eval_circuit": ([_vp, ctypes.POINTER(MkCircuit), _vp, _vp, _sz, _sz, _i, _vp], _i),
+    "mk_blind_rotate": ([_vp, _vp, _vp, _sz, _i, _i, _vp], _i),
+    "mk_extract_keyswitch": ([_vp, _vp, _vp, _sz, _sz, _vp], _i),
+    "mk_build_operator": ([_i, _i, ctypes.POINTER(MkGate), ctypes.POINTER(ctypes.c_int32),
+                           ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                           ctypes.POINTER(ctypes.c_int32)], _i),
+    "mk_last_error": ([], ctypes.c_char_p),
+    "mk_free": ([_vp], None),
+}
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(_L, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+EXPORTED = tuple(_SIGS)
+
+
+class MkError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (code %d)" % (msg, code))
+        self.code = code
+
+
+def _check(rc):
+    if rc != MK_OK:
+        raise MkError(rc, _L.mk_last_error().decode())
+
+
+def _stream(stream):
+    """hipStream_t handle of a torch stream (current stream if None)."""
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _host(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+@dataclass(frozen=True)
+class Params:
+    k: int
+    n: int
+    N: int
+    bk_ell: int
+    ks_t: int
+    bk_noise_log2: int
+    ks_noise_log2: int
+    lwe_noise_log2: int
+    bk_log_base: int = 8
+    ks_log_base: int = 2
+
+    def c(self) -> MkParams:
+        return MkParams(self.k, self.n, self.N, self.bk_log_base, self.bk_ell,
+                        self.ks_log_base, self.ks_t, self.bk_noise_log2,
+                        self.ks_noise_log2, self.lwe_noise_log2)
+
+    @property
+    def lwe_words(self):
+        return self.k * self.n + 1
+
+
+class Context:
+    """Owns an mk_ctx: keys on the host and the evaluation key on the GPU."""
+
+    def __init__(self, params: Params, crs_seed: int):
+        self.params = params
+        h = ctypes.c_void_p()
+        _check(_L.mk_setup(ctypes.byref(params.c()), crs_seed, ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _L.mk_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    # ---- host ----
+    def keygen(self, party: int, seed: int):
+        _check(_L.mk_keygen(self._h, party, seed))
+
+    def export_keys(self, party: int) -> bytes:
+        n = ctypes.c_size_t(0)
+        _check(_L.mk_export_keys(self._h, party, None, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        _check(_L.mk_export_keys(self._h, party, buf, ctypes.byref(n)))
+        return buf.raw
+
+    def import_keys(self, party: int, data: bytes):
+        buf = ctypes.create_string_buffer(bytes(data), len(data))
+        _check(_L.mk_import_keys(self._h, party, buf, len(data)))
+
+    def upload(self, stream=None):
+        _check(_L.mk_upload_eval_key(self._h, _stream(stream)))
+
+    def encrypt(self, party: int, bits, seed: int, stride: int | None = None) -> np.ndarray:
+        b, bp = _host(bits, np.uint8)
+        stride = stride or self.params.lwe_words
+        out = np.zeros((b.shape[0], stride), np.uint32)
+        _check(_L.mk_encrypt(self._h, party, bp, b.shape[0], seed,
+                             out.ctypes.data_as(ctypes.c_void_p), stride))
+        return out
+
+    def decrypt(self, ct) -> np.ndarray:
+        c, cp = _host(ct, np.uint32)
+        c = c.reshape(-1, c.shape[-1])
+        out = np.zeros(c.shape[0], np.uint8)
+        _check(_L.mk_decrypt(self._h, c.ctypes.data_as(ctypes.c_void_p), c.shape[0],
+                             c.shape[1], out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def trivial(self, bits, stride: int | None = None) -> np.ndarray:
+        b, bp = _host(bits, np.uint8)
+        stride = stride or self.params.lwe_words
+        out = np.zeros((b.shape[0], stride), np.uint32)
+        _check(_L.mk_trivial(self._h, bp, b.shape[0], out.ctypes.data_as(ctypes.c_void_p), stride))
+        return out
+
+    # ---- device (torch tensors) ----
+    def lwe_not(self, inp, out, stream=None):
+        _check(_L.mk_not(self._h, _ptr(inp), _ptr(out), inp.shape[0], inp.shape[1],
+                         _stream(stream)))
+
+    def bootstrap_gate(self, types, in1, in2, out, path=PATH_MFMA_I8, stream=None):
+        assert in1.shape == in2.shape == out.shape and types.shape[0] == in1.shape[0]
+        _check(_L.mk_bootstrap_gate(self._h, _ptr(types), _ptr(in1), _ptr(in2), _ptr(out),
+                                    in1.shape[0], in1.shape[1], path, _stream(stream)))
+
+    def blind_rotate(self, abar, acc, max_steps=-1, path=PATH_MFMA_I8, stream=None):
+        _check(_L.mk_blind_rotate(self._h, _ptr(abar), _ptr(acc), abar.shape[0], max_steps,
+                                  path, _stream(stream)))
+
+    def extract_keyswitch(self, acc, out, stream=None):
+        _check(_L.mk_extract_keyswitch(self._h, _ptr(acc), _ptr(out), acc.shape[0],
+                                       out.shape[1], _stream(stream)))
+
+    def eval_circuit(self, circuit: "Circuit", inp, out, path=PATH_MFMA_I8, stream=None):
+        batch = inp.shape[1]
+        _check(_L.mk_eval_circuit(self._h, ctypes.byref(circuit.c()), _ptr(inp), _ptr(out),
+                                  batch, inp.shape[2], path, _stream(stream)))
+
+
+@dataclass
+class Circuit:
+    """A netlist in the layout of mk_circuit (arrays of int32)."""
+    n_wires: int
+    inputs: np.ndarray
+    outputs: np.ndarray
+    gates: np.ndarray        # int32[n_gates, 4]: type, in1, in2, out
+
+    def c(self) -> MkCircuit:
+        self._keep = (np.ascontiguousarray(self.inputs, np.int32),
+                      np.ascontiguousarray(self.outputs, np.int32),
+                      np.ascontiguousarray(self.gates, np.int32))
+        i, o, g = self._keep
+        return MkCircuit(self.n_wires,
+                         len(i), i.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                         len(o), o.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                         len(g), g.ctypes.data_as(ctypes.POINTER(MkGate)))
+
+
+OP_ADD, OP_SUB, OP_MUL, OP_DIV = 0, 1, 2, 3
+
+
+def build_operator(op: int, kbits: int) -> Circuit:
+    """Netlist of a k-bit operator from the library's builders."""
+    ng, nw = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(_L.mk_build_operator(op, kbits, None, ctypes.byref(ng), ctypes.byref(nw), None, None))
+    gates = np.zeros((ng.value, 4), np.int32)
+    n_in = 2 * kbits
+    n_out = {OP_ADD: kbits, OP_SUB: kbits, OP_MUL: 2 * kbits, OP_DIV: 2 * kbits}[op]
+    inputs = np.zeros(n_in, np.int32)
+    outputs = np.zeros(n_out, np.int32)
+    P32 = ctypes.POINTER(ctypes.c_int32)
+    _check(_L.mk_build_operator(op, kbits, gates.ctypes.data_as(ctypes.POINTER(MkGate)),
+                                ctypes.byref(ng), ctypes.byref(nw),
+                                inputs.ctypes.data_as(P32), outputs.ctypes.data_as(P32)))
+    return Circuit(nw.value, inputs, outputs, gates)

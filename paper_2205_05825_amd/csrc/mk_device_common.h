@@ -1,0 +1,29 @@
+// Declarations shared by the device translation units (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "mk_internal.h"
+
+namespace mk {
+
+// Offset of the signed base-2^8 gadget decomposition with `ell` digits:
+// 2^(31-8 ell) (rounding) + sum_p 2^(32-8p) * 2^7 (digit bias), so that
+// digit_p = ((x + offset) >> (32-8p) & 255) - 128.
+__host__ __device__ inline uint32_t decomp_offset(int ell) {
+    uint32_t off = 1u << (31 - 8 * ell);
+    for (int p = 1; p <= ell; ++p) off += 128u << (32 - 8 * p);
+    return off;
+}
+
+int hip_fail(hipError_t e, const char *what);
+int ensure_scratch(mk_ctx *ctx, size_t bytes);
+
+// Int8-MFMA path (mk_mfma.hip).
+int mfma_upload(mk_ctx *ctx, const std::vector<uint32_t> &evk, hipStream_t s);
+int launch_br_mfma(mk_ctx *ctx, const uint32_t *abar, uint32_t *acc, size_t count, int steps,
+                   hipStream_t s);
+
+}  // namespace mk

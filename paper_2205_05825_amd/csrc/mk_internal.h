@@ -1,0 +1,67 @@
+// Internal declarations shared by the host and device translation units of
+// the library.  Not part of the C ABI.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "mk_tfhe.h"
+
+namespace mk {
+
+// Sets the thread-local error message and returns `code`.
+int fail(int code, const std::string &msg);
+
+struct HostPartyKeys {
+    bool present = false;
+    std::vector<uint8_t> s;      // [n]
+    std::vector<uint8_t> z;      // [N]
+    std::vector<uint32_t> pk;    // [ell][N]
+    std::vector<uint32_t> bk;    // [n][3][ell][N]
+    std::vector<uint32_t> ks;    // [N][t][B'-1][n+1]
+};
+
+// Device copies of the evaluation key, built by mk_upload_eval_key.
+struct DeviceKeys {
+    bool uploaded = false;
+    int device = -1;
+    // Plain path: every key polynomial K stored in extended form [-K | K]
+    // (2N words) so that the negacyclic Toeplitz entry T[m][p] = K'[m-p] is
+    // the word at index N + m - p.
+    uint32_t *bk_ext = nullptr;   // [k][n][3][ell][2N]
+    uint32_t *evk_ext = nullptr;  // [k+1][ell][2N]
+    // Int8-MFMA path: limb-planar windows (see mk_device.hip).
+    int8_t *bk_win = nullptr;
+    int8_t *evk_win = nullptr;
+    size_t bk_win_bytes = 0, evk_win_bytes = 0;
+    uint32_t *ks = nullptr;       // [k][N][t][B'-1][n+1]
+    // Scratch for the gate pipeline, grown on demand.
+    void *scratch = nullptr;
+    size_t scratch_bytes = 0;
+};
+
+}  // namespace mk
+
+struct mk_ctx {
+    mk_params p{};
+    uint64_t crs_seed = 0;
+    std::vector<uint32_t> crs;   // [ell][N]
+    std::vector<mk::HostPartyKeys> parties;
+    mk::DeviceKeys dev;
+};
+
+namespace mk {
+
+inline size_t lwe_words(const mk_params &p) { return (size_t)p.k * p.n + 1; }
+inline int ks_base(const mk_params &p) { return 1 << p.ks_log_base; }
+inline size_t ks_rows(const mk_params &p) {
+    return (size_t)p.N * p.ks_t * (ks_base(p) - 1);
+}
+
+// Device side (mk_device.hip).
+int device_upload(mk_ctx *ctx, void *stream);
+void device_release(mk_ctx *ctx);
+
+}  // namespace mk

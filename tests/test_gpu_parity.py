@@ -1,0 +1,185 @@
+"""GPU parity of the bootstrapping pipeline against the oracle, bit for bit,
+through the C ABI (needs an MI355X)."""
+import numpy as np
+import pytest
+
+import mk_inputs as mi
+from oracle import params as OP
+from oracle import tfhe
+from tests import helpers
+
+pytestmark = pytest.mark.gpu
+
+PATHS = [0]   # MK_PATH_I32; the int8-MFMA path joins once built
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+def _gates_on_gpu(torch, ctx, types, c1, c2, path):
+    d = torch.device("cuda:0")
+    t = torch.from_numpy(np.ascontiguousarray(types, np.uint8)).to(d)
+    a = torch.from_numpy(np.ascontiguousarray(c1).view(np.int32)).to(d)
+    b = torch.from_numpy(np.ascontiguousarray(c2).view(np.int32)).to(d)
+    out = torch.full_like(a, -1)
+    ctx.bootstrap_gate(t, a, b, out, path=path)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().view(np.uint32)
+
+
+def _workload(K, types, m1, m2, seed, stride=None):
+    P = K.params
+    c1 = tfhe.encrypt(K, 0, m1, seed=seed)
+    c2 = tfhe.encrypt(K, P.k - 1 if P.k > 1 else 0, m2, seed=seed + 1)
+    if stride:
+        pad = np.zeros((len(types), stride - P.lwe_words), np.uint32)
+        c1, c2 = np.hstack([c1, pad]), np.hstack([c2, pad])
+    return c1, c2
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_c1_truth_table_workload(torch_cuda, path):
+    """4 XOR + 4 NAND on every input pair, seed 0: every output word."""
+    K, ctx = helpers.gpu_world("C1")
+    types, m1, m2 = mi.truth_table(gates=(mi.XOR, mi.NAND))
+    c1, c2 = _workload(K, types, m1, m2, seed=0)
+    got = _gates_on_gpu(torch_cuda, ctx, types, c1, c2, path)
+    ref = helpers.oracle_gates("C1", types, c1, c2)
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_c1b_random_batch_decrypts_and_matches(torch_cuda, path):
+    K, ctx = helpers.gpu_world("C1B")
+    types, m1, m2 = mi.gate_batch(77, seed=31)
+    c1, c2 = _workload(K, types, m1, m2, seed=40)
+    got = _gates_on_gpu(torch_cuda, ctx, types, c1, c2, path)
+    ref = helpers.oracle_gates("C1B", types, c1, c2)
+    assert np.array_equal(got, ref)
+    want = [mi.plain_gate(int(t), int(a), int(b)) for t, a, b in zip(types, m1, m2)]
+    assert tfhe.decrypt(K, got).tolist() == want
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_blind_rotate_stage_c1(torch_cuda, path):
+    """Arbitrary modulus-switched inputs, including zero shifts."""
+    K, ctx = helpers.gpu_world("C1")
+    P = K.params
+    rng = np.random.default_rng(3)
+    abar = rng.integers(0, 2 * P.N, (5, P.lwe_words)).astype(np.uint32)
+    abar[1, 1::2] = 0                    # skipped steps
+    abar[2, :] = 0
+    abar[3, :] = 2 * P.N - 1
+    d = torch_cuda.device("cuda:0")
+    ta = torch_cuda.from_numpy(abar.view(np.int32)).to(d)
+    acc = torch_cuda.zeros((5, (P.k + 1) * P.N), dtype=torch_cuda.int32, device=d)
+    ctx.blind_rotate(ta, acc, path=path)
+    torch_cuda.cuda.synchronize()
+    got = acc.cpu().numpy().view(np.uint32).reshape(5, P.k + 1, P.N)
+    for g in range(5):
+        assert np.array_equal(got[g], tfhe.blind_rotate(K, abar[g].astype(np.int64))), g
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_blind_rotate_partial_c2(torch_cuda, path):
+    """First 12 CMux steps of 96 C2 gates (several workgroups, ragged)."""
+    K, ctx = helpers.gpu_world("C2")
+    P = K.params
+    rng = np.random.default_rng(4)
+    cnt = 96
+    abar = rng.integers(0, 2 * P.N, (cnt, P.lwe_words)).astype(np.uint32)
+    d = torch_cuda.device("cuda:0")
+    ta = torch_cuda.from_numpy(abar.view(np.int32)).to(d)
+    acc = torch_cuda.zeros((cnt, (P.k + 1) * P.N), dtype=torch_cuda.int32, device=d)
+    ctx.blind_rotate(ta, acc, max_steps=12, path=path)
+    torch_cuda.cuda.synchronize()
+    got = acc.cpu().numpy().view(np.uint32).reshape(cnt, P.k + 1, P.N)
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(8) as ex:
+        refs = list(ex.map(lambda g: tfhe.blind_rotate(K, abar[g].astype(np.int64), max_steps=12),
+                           range(cnt)))
+    for g in range(cnt):
+        assert np.array_equal(got[g], refs[g]), g
+
+
+def test_extract_keyswitch_stage_c2(torch_cuda):
+    K, ctx = helpers.gpu_world("C2")
+    P = K.params
+    rng = np.random.default_rng(5)
+    cnt = 6
+    acc = rng.integers(0, 1 << 32, (cnt, (P.k + 1) * P.N), dtype=np.uint64).astype(np.uint32)
+    acc[1] = 0
+    d = torch_cuda.device("cuda:0")
+    tacc = torch_cuda.from_numpy(acc.view(np.int32)).to(d)
+    stride = P.lwe_words + 3
+    out = torch_cuda.full((cnt, stride), 7, dtype=torch_cuda.int32, device=d)
+    ctx.extract_keyswitch(tacc, out)
+    torch_cuda.cuda.synchronize()
+    got = out.cpu().numpy().view(np.uint32)
+    for g in range(cnt):
+        big = tfhe.sample_extract(acc[g].reshape(P.k + 1, P.N))
+        big[0] = np.uint32((int(big[0]) + tfhe.EIGHTH) & 0xFFFFFFFF)
+        assert np.array_equal(got[g, :P.lwe_words], tfhe.key_switch(K, big)), g
+        assert (got[g, P.lwe_words:] == 7).all()      # padding untouched
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_c2_batch_1024(torch_cuda, path):
+    """The 1024-gate mixed workload: all outputs decrypt to the plaintext
+    gate, and sampled outputs equal the oracle's word for word."""
+    K, ctx = helpers.gpu_world("C2")
+    types, m1, m2 = mi.gate_batch(1024, seed=2)
+    c1, c2 = _workload(K, types, m1, m2, seed=200)
+    got = _gates_on_gpu(torch_cuda, ctx, types, c1, c2, path)
+    want = [mi.plain_gate(int(t), int(a), int(b)) for t, a, b in zip(types, m1, m2)]
+    assert tfhe.decrypt(K, got).tolist() == want
+    idx = [0, 1, 511, 1023] + list(np.random.default_rng(6).choice(1024, 4, replace=False))
+    ref = helpers.oracle_gates("C2", types, c1, c2, idx)
+    assert np.array_equal(got[idx], ref)
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_edge_cases(torch_cuda, path):
+    K, ctx = helpers.gpu_world("C1")
+    P = K.params
+    d = torch_cuda.device("cuda:0")
+    # empty batch is a no-op
+    e = torch_cuda.zeros((0, P.lwe_words), dtype=torch_cuda.int32, device=d)
+    ctx.bootstrap_gate(torch_cuda.zeros(0, dtype=torch_cuda.uint8, device=d), e, e, e, path=path)
+    # padded stride, single gate, trivial (noiseless) inputs: all mask shifts 0
+    stride = P.lwe_words + 5
+    for types, c1, c2 in [
+        (np.array([mi.AND], np.uint8), *_workload(K, [mi.AND], [1], [1], 9, stride)),
+        (np.array([mi.XOR, mi.NOR], np.uint8),
+         np.hstack([tfhe.trivial(P, [1, 0]), np.zeros((2, 5), np.uint32)]),
+         np.hstack([tfhe.trivial(P, [0, 0]), np.zeros((2, 5), np.uint32)])),
+    ]:
+        got = _gates_on_gpu(torch_cuda, ctx, types, c1, c2, path)
+        ref = helpers.oracle_gates("C1", types, c1, c2)
+        assert np.array_equal(got[:, :P.lwe_words], ref)
+        assert (got[:, P.lwe_words:] == 0xFFFFFFFF).all()
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_repeat_is_deterministic(torch_cuda, path):
+    K, ctx = helpers.gpu_world("C1")
+    types, m1, m2 = mi.gate_batch(300, seed=8)
+    c1, c2 = _workload(K, types, m1, m2, seed=80)
+    a = _gates_on_gpu(torch_cuda, ctx, types, c1, c2, path)
+    b = _gates_on_gpu(torch_cuda, ctx, types, c1, c2, path)
+    assert np.array_equal(a, b)
+
+
+def test_not_gate(torch_cuda):
+    K, ctx = helpers.gpu_world("C1")
+    c = tfhe.encrypt(K, 0, [0, 1, 1], seed=5)
+    d = torch_cuda.device("cuda:0")
+    t = torch_cuda.from_numpy(c.view(np.int32)).to(d)
+    out = torch_cuda.empty_like(t)
+    ctx.lwe_not(t, out)
+    torch_cuda.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy().view(np.uint32), tfhe.lwe_not(c))

@@ -1,0 +1,103 @@
+"""Host-side checks of the C-ABI library (CPU only, no GPU calls):
+exported symbols, keygen/encryption parity with the oracle, serialisation
+and error codes."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import params as OP
+from oracle import tfhe
+from tests import helpers
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "mk_tfhe.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mk_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2205_05825_amd as mk
+    lib = ctypes.CDLL(mk.LIB_PATH)
+    declared = _declared_symbols()
+    assert len(declared) >= 16
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(declared) == set(mk.EXPORTED)
+
+
+@pytest.mark.parametrize("name", ["C1", "TOY"])
+def test_keygen_bytes_match_oracle(name):
+    helpers.assert_same_keys(name)
+
+
+@pytest.mark.slow
+def test_keygen_bytes_match_oracle_c2():
+    helpers.assert_same_keys("C2")
+
+
+def test_encrypt_matches_oracle_and_decrypts():
+    K = helpers.oracle_keys("C1")
+    ctx = helpers.lib_context("C1")
+    rng = np.random.default_rng(0)
+    bits = rng.integers(0, 2, 100).astype(np.uint8)
+    for party in range(OP.C1.k):
+        got = ctx.encrypt(party, bits, seed=1000 + party)
+        ref = tfhe.encrypt(K, party, bits, seed=1000 + party)
+        assert np.array_equal(got, ref)
+        assert np.array_equal(ctx.decrypt(got), bits)
+        assert np.array_equal(tfhe.decrypt(K, got), bits)
+    # padded stride: extra words are zero, the rest identical
+    got = ctx.encrypt(1, bits[:5], seed=3, stride=OP.C1.lwe_words + 7)
+    ref = tfhe.encrypt(K, 1, bits[:5], seed=3)
+    assert np.array_equal(got[:, :OP.C1.lwe_words], ref) and not got[:, OP.C1.lwe_words:].any()
+    assert np.array_equal(ctx.decrypt(got), bits[:5])
+
+
+def test_trivial_matches_oracle():
+    ctx = helpers.lib_context("C1")
+    bits = np.array([0, 1, 1], np.uint8)
+    assert np.array_equal(ctx.trivial(bits), tfhe.trivial(OP.C1, bits))
+
+
+def test_export_import_roundtrip():
+    import paper_2205_05825_amd as mk
+    src = helpers.lib_context("TOY")
+    dst = mk.Context(helpers.lib_params(OP.TOY), 12345)
+    for p in range(-1, OP.TOY.k):
+        dst.import_keys(p, src.export_keys(p))
+        assert dst.export_keys(p) == src.export_keys(p)
+    c = src.encrypt(0, [1, 0, 1], seed=4)
+    assert dst.decrypt(c).tolist() == [1, 0, 1]
+
+
+def test_error_codes():
+    import paper_2205_05825_amd as mk
+    bad = mk.Params(k=2, n=64, N=100, bk_ell=2, ks_t=6, bk_noise_log2=20,
+                    ks_noise_log2=20, lwe_noise_log2=12)
+    with pytest.raises(mk.MkError) as e:
+        mk.Context(bad, 0)
+    assert e.value.code == -5
+    b9 = mk.Params(k=2, n=560, N=1024, bk_ell=3, ks_t=8, bk_noise_log2=30,
+                   ks_noise_log2=15, lwe_noise_log2=15, bk_log_base=9)
+    with pytest.raises(mk.MkError) as e:        # Table 7's B = 2^9: digits not int8
+        mk.Context(b9, 0)
+    assert e.value.code == -5
+    ctx = mk.Context(helpers.lib_params(OP.TOY), 1)
+    with pytest.raises(mk.MkError) as e:
+        ctx.keygen(5, 0)
+    assert e.value.code == -1
+    with pytest.raises(mk.MkError) as e:
+        ctx.encrypt(0, [1], seed=0)
+    assert e.value.code == -4
+    with pytest.raises(mk.MkError) as e:
+        ctx.import_keys(0, b"\0" * 10)
+    assert e.value.code == -1
+    with pytest.raises(mk.MkError) as e:        # no keys: upload refused on the host
+        ctx.upload(stream=0)
+    assert e.value.code == -4
