@@ -1,0 +1,203 @@
+"""Benchmark: bootstrapped multi-key gates per second on one MI355X.
+
+Workload (default): a batch of 1024 independent bootstrapped gates, types
+uniform over AND/OR/NOR/XOR/XNOR/NAND, uniform input bits, 2 parties (input 1
+encrypted by party 0, input 2 by party 1), n=560, N=1024, gadget base 2^8 with
+ell=3, key-switching base 2^2 with t=8 (Table 7 shape with B = 2^8).  One
+"step" is the whole gate pipeline on the batch: pre-combination and modulus
+switch, blind rotation (k*n = 1120 hybrid-product CMux steps), sample
+extraction and multi-key key switching.  Ciphertexts and keys are resident in
+HBM before timing starts; key generation and upload are excluded.
+
+Prints one JSON line.  The headline value is the int8-MFMA path; the plain
+32-bit integer path is timed on the same batch and reported beside it, and
+the two outputs are checked to be bit-identical before timing.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import mk_inputs as mi  # noqa: E402
+
+C2 = dict(k=2, n=560, N=1024, bk_ell=3, ks_t=8, bk_noise_log2=30, ks_noise_log2=15,
+          lwe_noise_log2=15)
+SEED = 2
+BATCH = 1024
+PEAK_INT8_OPS = 5.0e15          # MI355X dense int8 MFMA
+# An exact Torus32 multiply-add on the vector ALU takes at least two full-rate
+# 24-bit multiply-adds (one per half of the key word): 256 CUs x 64 lanes x
+# 2.4 GHz / 2.
+PEAK_VALU_TORUS_MACS = 256 * 64 * 2.4e9 / 2
+
+
+def macs_per_gate(p):
+    """Exact Torus32 multiply-adds of one blind rotation: k*n CMux steps, each
+    (2k+4)*ell negacyclic products of N^2 multiply-adds."""
+    return p["k"] * p["n"] * (2 * p["k"] + 4) * p["bk_ell"] * p["N"] ** 2
+
+
+# ------------------------------------------------------- CPU baseline ----
+_CPU = {}
+
+
+def _cpu_gate(g):
+    from oracle import tfhe
+    K, evk, types, c1, c2 = _CPU["state"]
+    return tfhe.bootstrapped_gate(K, int(types[g]), c1[g], c2[g], evk)
+
+
+def cpu_baseline(gates_per_core: int):
+    """The oracle, as it stands, on a bounded sample of the same workload,
+    one process per host core (fork before any GPU use)."""
+    import multiprocessing as mp
+
+    from oracle import params as OP
+    from oracle import tfhe
+    K = tfhe.generate(OP.C2, SEED)
+    types, m1, m2 = mi.gate_batch(BATCH, seed=SEED)
+    c1 = tfhe.encrypt(K, 0, m1, seed=200)
+    c2 = tfhe.encrypt(K, 1, m2, seed=201)
+    _CPU["state"] = (K, K.evaluation_key(), types, c1, c2)
+    cores = min(os.cpu_count() or 1, 16)
+    sample = list(range(cores * gates_per_core))
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        outs = pool.map(_cpu_gate, sample, chunksize=1)
+    dt = time.perf_counter() - t0
+    want = [mi.plain_gate(int(types[g]), int(m1[g]), int(m2[g])) for g in sample]
+    ok = tfhe.decrypt(K, np.stack(outs)).tolist() == want
+    return {"value": len(sample) / dt, "unit": "gates/s", "cores": cores, "kind": "oracle",
+            "sample": "%d of the %d workload gates (%d per core), %.1f s wall, decrypt %s"
+                      % (len(sample), BATCH, gates_per_core, dt, "ok" if ok else "FAILED")}
+
+
+# ---------------------------------------------------------------- GPU ----
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--plain-steps", type=int, default=1)
+    ap.add_argument("--path", choices=["mfma", "i32"], default="mfma")
+    ap.add_argument("--cpu-gates-per-core", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on exactly one GPU (the path is per-GPU; "
+              "--gpus %d is not supported)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_gates_per_core)
+
+    import torch
+
+    import paper_2205_05825_amd as mk
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    P = mk.Params(**C2)
+    ctx = mk.Context(P, SEED)
+    for i in range(P.k):
+        ctx.keygen(i, (SEED + 1 + i) & 0xFFFFFFFFFFFFFFFF)
+    ctx.upload()
+    types, m1, m2 = mi.gate_batch(BATCH, seed=SEED)
+    c1 = ctx.encrypt(0, m1, seed=200)
+    c2 = ctx.encrypt(1, m2, seed=201)
+    t = torch.from_numpy(types).to(dev)
+    a = torch.from_numpy(c1.view(np.int32)).to(dev)
+    b = torch.from_numpy(c2.view(np.int32)).to(dev)
+    want = np.array([mi.plain_gate(int(x), int(y), int(z)) for x, y, z in zip(types, m1, m2)])
+
+    def run(path, out):
+        ctx.bootstrap_gate(t, a, b, out, path=path)
+
+    paths = {"mfma": mk.PATH_MFMA_I8, "i32": mk.PATH_I32}
+    head = paths[args.path]
+    # correctness gate before timing: outputs decrypt and both paths agree
+    outs = {}
+    for name, path in paths.items():
+        o = torch.zeros_like(a)
+        try:
+            run(path, o)
+        except mk.MkError as e:
+            if path == mk.PATH_MFMA_I8 and head != path:
+                continue
+            raise
+        torch.cuda.synchronize()
+        outs[name] = o.cpu().numpy().view(np.uint32)
+        assert np.array_equal(ctx.decrypt(outs[name]), want), name
+    if len(outs) == 2:
+        assert np.array_equal(outs["mfma"], outs["i32"]), "paths differ"
+
+    def timed(path, steps, warmup, level=2):
+        out = torch.zeros_like(a)
+        for _ in range(warmup):
+            run(path, out)
+        torch.cuda.synchronize()
+        ctx.get_profile(reset=True)
+        ctx.set_profiling(level)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            run(path, out)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ctx.set_profiling(0)
+        ms, launches = ctx.get_profile(reset=True)
+        return dt / steps, ms, launches
+
+    sec, ms, ln = timed(head, args.steps, args.warmup)
+    value = BATCH / sec
+    br_ms = ms[1] / max(ln[1], 1)
+    macs = macs_per_gate(C2) * BATCH
+    if head == mk.PATH_MFMA_I8:
+        # dominant kernel: the stage-1 GEMM, (2k+2)*ell of the (2k+4)*ell
+        # products of every CMux step, int8 ops = 2 * 4 limbs * MACs
+        k, ell, N = C2["k"], C2["bk_ell"], C2["N"]
+        g1_ops = 8 * (2 * k + 2) * ell * N * N * BATCH
+        g1_ms = ms[4] / max(ln[4], 1)
+        achieved = g1_ops / (g1_ms * 1e-3)
+        roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_INT8_OPS / 1e12,
+                "unit": "TOP/s", "frac": achieved / PEAK_INT8_OPS, "traffic": None,
+                "kernel": "mfma_gemm1_kernel", "avg_launch_ms": g1_ms,
+                "launches": ln[4],
+                "whole_rotation_tops": 8 * macs / (br_ms * 1e-3) / 1e12}
+    else:
+        achieved = macs / (br_ms * 1e-3)
+        roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_TORUS_MACS / 1e12,
+                "unit": "T Torus32-MAC/s", "frac": achieved / PEAK_VALU_TORUS_MACS, "traffic": None,
+                "kernel": "br_plain_kernel", "avg_launch_ms": br_ms}
+    res = {
+        "metric": "bootstrapped MK gates/sec on 1 MI355X (int8-MFMA batched vs int32 plain), bit-exact",
+        "value": value, "unit": "gates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "int8" if head == mk.PATH_MFMA_I8 else "int32", "data": "synthetic",
+        "config": {"workload": "1024 mixed bootstrapped MK gates (AND/OR/NOR/XOR/XNOR/NAND), "
+                               "k=2 n=560 N=1024 B=2^8 ell=3 B'=2^2 t=8",
+                   "global_batch": BATCH, "path": args.path, "parallelism": "single GPU"},
+        "stage_ms_per_step": {"precombine": ms[0] / args.steps, "blind_rotate": ms[1] / args.steps,
+                              "extract_keyswitch": ms[2] / args.steps,
+                              "mfma_gemm1": ms[4] / args.steps, "mfma_gemm2": ms[5] / args.steps,
+                              "rotdec": ms[6] / args.steps, "wdec": ms[7] / args.steps},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    if head == mk.PATH_MFMA_I8 and "i32" in outs and args.plain_steps > 0:
+        psec, pms, pln = timed(mk.PATH_I32, args.plain_steps, 0, level=1)
+        res["plain_i32"] = {"value": BATCH / psec, "ms_per_step": psec * 1e3,
+                            "blind_rotate_ms": pms[1] / max(pln[1], 1)}
+        res["mfma_vs_plain"] = value / (BATCH / psec)
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -205,6 +205,18 @@ int mk_extract_keyswitch(mk_ctx *ctx, const uint32_t *acc_dev,
 int mk_build_operator(int op, int kbits, mk_gate *gates, int32_t *n_gates,
                       int32_t *n_wires, int32_t *inputs, int32_t *outputs);
 
+/* Kernel timing.  With level 1, every pipeline stage is bracketed by HIP
+ * events recorded on the caller's stream; level 2 also brackets each kernel
+ * of the int8-MFMA rotation; level 0 turns timing off.  mk_get_profile waits
+ * for the events and returns accumulated milliseconds and launch counts for
+ * MK_PROFILE_SLOTS slots: [0] pre-combination, [1] blind rotation (whole),
+ * [2] extraction + key switching, [3] circuit bookkeeping, [4] MFMA stage-1
+ * GEMM, [5] MFMA stage-2 GEMM, [6] rotate + decompose, [7] w decompose.
+ * reset != 0 clears the accumulators.  Errors: MK_EINVAL. */
+#define MK_PROFILE_SLOTS 8
+int mk_set_profiling(mk_ctx *ctx, int level);
+int mk_get_profile(mk_ctx *ctx, double *ms, int64_t *launches, int reset);
+
 /* Thread-local description of the last error on this thread. */
 const char *mk_last_error(void);
 

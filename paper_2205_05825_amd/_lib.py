@@ -65,6 +65,8 @@ _SIGS = {
     "mk_build_operator": ([_i, _i, ctypes.POINTER(MkGate), ctypes.POINTER(ctypes.c_int32),
                            ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                            ctypes.POINTER(ctypes.c_int32)], _i),
+    "mk_set_profiling": ([_vp, _i], _i),
+    "mk_get_profile": ([_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), _i], _i),
     "mk_last_error": ([], ctypes.c_char_p),
     "mk_free": ([_vp], None),
 }
@@ -186,6 +188,19 @@ class Context:
         out = np.zeros((b.shape[0], stride), np.uint32)
         _check(_L.mk_trivial(self._h, bp, b.shape[0], out.ctypes.data_as(ctypes.c_void_p), stride))
         return out
+
+    # ---- profiling ----
+    def set_profiling(self, level: int):
+        """0 off, 1 pipeline stages, 2 stages and each MFMA-rotation kernel."""
+        _check(_L.mk_set_profiling(self._h, int(level)))
+
+    def get_profile(self, reset: bool = False):
+        """(ms[8], launches[8]): precombine, rotation, keyswitch, circuit,
+        MFMA gemm1, MFMA gemm2, rotate+decompose, w decompose."""
+        ms = (ctypes.c_double * 8)()
+        ln = (ctypes.c_int64 * 8)()
+        _check(_L.mk_get_profile(self._h, ms, ln, int(bool(reset))))
+        return list(ms), list(ln)
 
     # ---- device (torch tensors) ----
     def lwe_not(self, inp, out, stream=None):

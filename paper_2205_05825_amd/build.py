@@ -2,7 +2,8 @@
 
 Every call compiles every source (no stale objects).  Sources: csrc/*.cpp
 (host C++) and csrc/*.hip (device code), linked into one shared object next
-to this file.  Usage: python -m paper_2205_05825_amd.build
+to this file.  Usage: python paper_2205_05825_amd/build.py (run by path: the
+package itself refuses to import while the library is missing).
 """
 from __future__ import annotations
 

@@ -34,6 +34,38 @@ int hip_fail(hipError_t e, const char *what) {
         if (e_ != hipSuccess) return hip_fail(e_, what);     \
     } while (0)
 
+StageTimer::StageTimer(mk_ctx *c, int st, hipStream_t str) : ctx(c), stage(st), s(str) {
+    if (ctx->dev.profiling < (st >= 4 ? 2 : 1)) return;
+    if (hipEventCreate(&b) != hipSuccess || hipEventCreate(&e) != hipSuccess) {
+        b = e = nullptr;
+        return;
+    }
+    (void)hipEventRecord(b, s);
+}
+
+StageTimer::~StageTimer() {
+    if (!b) return;
+    (void)hipEventRecord(e, s);
+    ctx->dev.events[stage].emplace_back((void *)b, (void *)e);
+}
+
+static void drain_events(mk_ctx *ctx) {
+    DeviceKeys &D = ctx->dev;
+    for (int st = 0; st < MK_PROFILE_SLOTS; ++st) {
+        for (auto &pr : D.events[st]) {
+            hipEvent_t b = (hipEvent_t)pr.first, e = (hipEvent_t)pr.second;
+            float ms = 0;
+            if (hipEventSynchronize(e) == hipSuccess && hipEventElapsedTime(&ms, b, e) == hipSuccess) {
+                D.prof_ms[st] += ms;
+                D.prof_launches[st] += 1;
+            }
+            (void)hipEventDestroy(b);
+            (void)hipEventDestroy(e);
+        }
+        D.events[st].clear();
+    }
+}
+
 int ensure_scratch(mk_ctx *ctx, size_t bytes) {
     DeviceKeys &D = ctx->dev;
     if (D.scratch_bytes >= bytes) return MK_OK;
@@ -64,8 +96,9 @@ static int check_uploaded(const mk_ctx *ctx) {
 // -------------------------------------------------------------- upload ---
 
 void device_release(mk_ctx *ctx) {
+    drain_events(ctx);
     DeviceKeys &D = ctx->dev;
-    void *ptrs[] = {D.bk_ext, D.evk_ext, D.bk_win, D.evk_win, D.ks, D.scratch};
+    void *ptrs[] = {D.bk_ext, D.evk_ext, D.bk_win, D.evk_win, D.ks, D.scratch, D.mfma_scratch};
     bool any = false;
     for (void *p : ptrs) any |= p != nullptr;
     if (any) {
@@ -73,7 +106,9 @@ void device_release(mk_ctx *ctx) {
         for (void *p : ptrs)
             if (p) (void)hipFree(p);
     }
+    const int prof = D.profiling;
     D = DeviceKeys();
+    D.profiling = prof;
 }
 
 template <class T>
@@ -337,6 +372,7 @@ static int launch_br_plain(mk_ctx *ctx, const uint32_t *abar, uint32_t *acc, siz
         BrPlainArgs b = a;
         b.abar = abar + off * (P.k * P.n + 1);
         b.acc_out = acc + off * K1 * P.N;
+        StageTimer tm(ctx, 1, s);
         hipLaunchKernelGGL(br_plain_kernel, dim3((unsigned)c), dim3(threads), lds, s, b);
         MK_HIP(hipGetLastError(), "br_plain launch");
     }
@@ -417,6 +453,7 @@ static int launch_extract_ks(mk_ctx *ctx, const uint32_t *acc, uint32_t *out, si
         KsArgs b = a;
         b.acc = acc + off * (P.k + 1) * P.N;
         b.out = out + off * stride;
+        StageTimer tm(ctx, 2, s);
         hipLaunchKernelGGL(extract_ks_kernel, dim3((unsigned)c), dim3(kKsThreads), lds, s, b);
         MK_HIP(hipGetLastError(), "extract_ks launch");
     }
@@ -444,8 +481,11 @@ int run_gates(mk_ctx *ctx, const uint8_t *types, const uint32_t *in1, const uint
     uint32_t *acc = (uint32_t *)((char *)ctx->dev.scratch + abar_bytes);
     const size_t total = count * words;
     const int log2_2N = __builtin_ctz(2 * P.N);
-    hipLaunchKernelGGL(precombine_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
-                       types, in1, in2, stride, (int)words, log2_2N, total, abar);
+    {
+        StageTimer tm(ctx, 0, s);
+        hipLaunchKernelGGL(precombine_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                           types, in1, in2, stride, (int)words, log2_2N, total, abar);
+    }
     MK_HIP(hipGetLastError(), "precombine launch");
     if ((rc = run_blind_rotate(ctx, abar, acc, count, P.k * P.n, path, s))) return rc;
     return launch_extract_ks(ctx, acc, out, count, stride, s);
@@ -460,6 +500,26 @@ extern "C" {
 int mk_upload_eval_key(mk_ctx *ctx, void *stream) {
     if (!ctx) return fail(MK_EINVAL, "mk_upload_eval_key: null context");
     return device_upload(ctx, stream);
+}
+
+int mk_set_profiling(mk_ctx *ctx, int level) {
+    if (!ctx || level < 0 || level > 2) return fail(MK_EINVAL, "mk_set_profiling: bad argument");
+    ctx->dev.profiling = level;
+    return MK_OK;
+}
+
+int mk_get_profile(mk_ctx *ctx, double *ms, int64_t *launches, int reset) {
+    if (!ctx) return fail(MK_EINVAL, "mk_get_profile: null context");
+    drain_events(ctx);
+    for (int st = 0; st < MK_PROFILE_SLOTS; ++st) {
+        if (ms) ms[st] = ctx->dev.prof_ms[st];
+        if (launches) launches[st] = ctx->dev.prof_launches[st];
+        if (reset) {
+            ctx->dev.prof_ms[st] = 0;
+            ctx->dev.prof_launches[st] = 0;
+        }
+    }
+    return MK_OK;
 }
 
 int mk_not(const mk_ctx *ctx, const uint32_t *in_dev, uint32_t *out_dev, size_t count,

@@ -19,6 +19,16 @@ __host__ __device__ inline uint32_t decomp_offset(int ell) {
 }
 
 int hip_fail(hipError_t e, const char *what);
+
+// Brackets a kernel launch with profiling events when enabled.
+struct StageTimer {
+    StageTimer(mk_ctx *ctx, int stage, hipStream_t s);
+    ~StageTimer();
+    mk_ctx *ctx;
+    int stage;
+    hipStream_t s;
+    hipEvent_t b = nullptr, e = nullptr;
+};
 int ensure_scratch(mk_ctx *ctx, size_t bytes);
 
 // Int8-MFMA path (mk_mfma.hip).

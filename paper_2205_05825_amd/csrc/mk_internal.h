@@ -5,6 +5,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "mk_tfhe.h"
@@ -37,9 +38,16 @@ struct DeviceKeys {
     int8_t *evk_win = nullptr;
     size_t bk_win_bytes = 0, evk_win_bytes = 0;
     uint32_t *ks = nullptr;       // [k][N][t][B'-1][n+1]
-    // Scratch for the gate pipeline, grown on demand.
+    // Profiling: event pairs per stage, accumulated on mk_get_profile.
+    int profiling = 0;
+    std::vector<std::pair<void *, void *>> events[MK_PROFILE_SLOTS];
+    double prof_ms[MK_PROFILE_SLOTS] = {};
+    int64_t prof_launches[MK_PROFILE_SLOTS] = {};
+    // Scratch for the gate pipeline and for the MFMA rotation, grown on demand.
     void *scratch = nullptr;
     size_t scratch_bytes = 0;
+    void *mfma_scratch = nullptr;
+    size_t mfma_scratch_bytes = 0;
 };
 
 }  // namespace mk

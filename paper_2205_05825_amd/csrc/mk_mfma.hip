@@ -1,12 +1,397 @@
-// Int8-MFMA blind rotation (K3).  Placeholder until the kernel lands.
+// Int8-MFMA blind rotation (K3) for gfx950.
+//
+// Every negacyclic product of a blind-rotation step is an exact integer
+// contraction  c_m = sum_p K'[m-p] u_p  (mod 2^32), where u are signed int8
+// gadget digits and K' is the key polynomial extended negacyclically
+// (K'[s] = K[s] for s >= 0, -K[s+N] for s < 0).  Each Torus32 entry K'[s] is
+// split into four signed 8-bit limbs, K'[s] = sum_t 2^(8t) L_t(K'[s]) mod 2^32
+// with L_t(x) = byte_t(x + 0x80808080) - 128, so
+//     c_m = sum_t 2^(8t) sum_p L_t(K'[m-p]) u_p   (mod 2^32)
+// and each inner sum is an int8 x int8 -> int32 matrix product, exact because
+// |sum| <= (k+1) * ell * N * 2^14 < 2^31 (checked at setup).
+//
+// Batched over G gates the products of one CMux step are GEMMs whose A
+// operand is a key Toeplitz matrix shared by all gates and whose B operand
+// holds the gates' digits (one column per gate).  A 32x32 tile of a Toeplitz
+// matrix at block row mb and block column kb only depends on d = mb - kb, so
+// the 2N/32 - 1 distinct tiles of every (key polynomial, limb) are stored
+// once, in the exact register layout of v_mfma_i32_32x32x32_i8 (lane l holds
+// row l%32 and the 16 K-values 16*(l/32)..+15), and loaded with one
+// coalesced 16-byte read per lane.
+//
+// Per CMux step (party i, bit l) four kernels run:
+//   rotdec : P_j = X^-a ACC_j - ACC_j per gate, decomposed into ell int8
+//            digit polynomials stored as MFMA B fragments; clears W.
+//   gemm1  : for every (unit, 128-row block, 32-gate tile): unit c'_j adds
+//            sum_l T(d_l) U_{j,l} into ACC_j; unit w_j adds
+//            sum_l T(b_{j,l}) U_{j,l} into W with wrapping atomics.
+//   wdec   : V = g^-1(W) as B fragments.
+//   gemm2  : ACC_0 += sum_l T(f0_l) V_l ;  ACC_{1+i} += sum_l T(f1_l) V_l.
+// Layouts (GP = gates padded to 32, GT = GP/32, NB = N/32, ND = 2 NB - 1):
+//   acc  u32 [GP][k+1][N]                 W  u32 [GP][N]
+//   U    i8  [k+1][ell][GT][NB][64][16]    V  i8  [ell][GT][NB][64][16]
+//   bk   i8  [k][n][3][ell][4][ND][64][16]
+//   evk  i8  [k+1][ell][4][ND][64][16]
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
 #include "mk_device_common.h"
 
 namespace mk {
 
-int mfma_upload(mk_ctx *, const std::vector<uint32_t> &, hipStream_t) { return MK_OK; }
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
 
-int launch_br_mfma(mk_ctx *, const uint32_t *, uint32_t *, size_t, int, hipStream_t) {
-    return fail(MK_EINVAL, "int8-MFMA path not built yet");
+constexpr int kTileBytes = 1024;  // one 32x32 int8 fragment (64 lanes x 16 B)
+
+#define MK_HIP(call, what)                               \
+    do {                                                 \
+        hipError_t e_ = (call);                          \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+// ------------------------------------------------------------ upload ----
+
+// Writes the ND diagonal tiles of 4 limbs for `npoly` polynomials given in
+// extended form ext[poly][2N] = [-K | K].  One thread per (poly, limb, diag,
+// lane) writes 16 bytes.
+__global__ void diag_tiles_kernel(const uint32_t *__restrict__ ext, int N, size_t npoly,
+                                  int8_t *__restrict__ out) {
+    const int NB = N / 32, ND = 2 * NB - 1;
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t total = npoly * 4 * ND * 64;
+    if (idx >= total) return;
+    const int lane = (int)(idx % 64);
+    const int d = (int)((idx / 64) % ND);
+    const int t = (int)((idx / (64 * ND)) % 4);
+    const size_t poly = idx / (64 * (size_t)ND * 4);
+    const uint32_t *e = ext + poly * 2 * N;
+    const int i = lane % 32, h = lane / 32;
+    uint32_t w[4] = {0, 0, 0, 0};
+    for (int b = 0; b < 16; ++b) {
+        const int s = 32 * (d - (NB - 1)) + i - (16 * h + b);   // in [-(N-1), N-1]
+        const uint32_t x = e[N + s] + 0x80808080u;
+        const uint32_t limb = ((x >> (8 * t)) & 255u) - 128u;   // int8 as byte
+        w[b / 4] |= (limb & 255u) << (8 * (b % 4));
+    }
+    reinterpret_cast<uint4 *>(out)[idx] = make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+int mfma_upload(mk_ctx *ctx, const std::vector<uint32_t> &evk, hipStream_t s) {
+    (void)evk;
+    const mk_params &P = ctx->p;
+    DeviceKeys &D = ctx->dev;
+    const int NB = P.N / 32, ND = 2 * NB - 1;
+    const size_t bk_polys = (size_t)P.k * P.n * 3 * P.bk_ell;
+    const size_t evk_polys = (size_t)(P.k + 1) * P.bk_ell;
+    D.bk_win_bytes = bk_polys * 4 * ND * kTileBytes;
+    D.evk_win_bytes = evk_polys * 4 * ND * kTileBytes;
+    if (hipMalloc((void **)&D.bk_win, D.bk_win_bytes) != hipSuccess) {
+        D.bk_win = nullptr;
+        return fail(MK_ENOMEM, "device allocation failed: MFMA bootstrapping-key tiles");
+    }
+    if (hipMalloc((void **)&D.evk_win, D.evk_win_bytes) != hipSuccess) {
+        D.evk_win = nullptr;
+        return fail(MK_ENOMEM, "device allocation failed: MFMA evaluation-key tiles");
+    }
+    // the extended plain-path keys are already queued for upload on `s`
+    const size_t per_poly = (size_t)4 * ND * 64;
+    const size_t chunk = (size_t)1 << 20;  // polys per launch bound
+    for (size_t p0 = 0; p0 < bk_polys; p0 += chunk) {
+        const size_t np = std::min(chunk, bk_polys - p0);
+        const size_t threads = np * per_poly;
+        hipLaunchKernelGGL(diag_tiles_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s,
+                           D.bk_ext + p0 * 2 * P.N, P.N, np, D.bk_win + p0 * 4 * ND * kTileBytes);
+        MK_HIP(hipGetLastError(), "diag tiles (bk) launch");
+    }
+    const size_t threads = evk_polys * per_poly;
+    hipLaunchKernelGGL(diag_tiles_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s,
+                       D.evk_ext, P.N, evk_polys, D.evk_win);
+    MK_HIP(hipGetLastError(), "diag tiles (evk) launch");
+    return MK_OK;
+}
+
+// ----------------------------------------------------------- kernels ----
+
+struct MfmaArgs {
+    int k, n, N, ell, log2N, GP, G;
+    uint32_t offset;          // gadget decomposition offset
+    const uint32_t *abar;     // [G][kn+1]
+    uint32_t *acc;            // [GP][k+1][N]
+    uint32_t *W;              // [GP][N]
+    int8_t *U;                // [k+1][ell][GT][NB][64][16]
+    int8_t *V;                // [ell][GT][NB][64][16]
+    const int8_t *bk;         // [k][n][3][ell][4][ND][1024]
+    const int8_t *evk;        // [k+1][ell][4][ND][1024]
+};
+
+// ACC_0 = X^-b v (v = -1/8 below N/2, +1/8 above), other polynomials 0.
+__global__ void mfma_init_kernel(MfmaArgs a) {
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int K1 = a.k + 1, N = a.N;
+    const size_t total = (size_t)a.GP * K1 * N;
+    if (idx >= total) return;
+    const int m = (int)(idx % N);
+    const int j = (int)((idx / N) % K1);
+    const int g = (int)(idx / ((size_t)K1 * N));
+    uint32_t v = 0;
+    if (j == 0 && g < a.G) {
+        const int s = m + (int)a.abar[(size_t)g * (a.k * a.n + 1)];
+        const uint32_t tv = (s & (N - 1)) < N / 2 ? 0xE0000000u : 0x20000000u;
+        v = ((s >> a.log2N) & 1) ? 0u - tv : tv;
+    }
+    a.acc[idx] = v;
+}
+
+__device__ __forceinline__ void store_digits16(int8_t *dst, const uint32_t (&y)[16], int shift) {
+    uint32_t w[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int e = 0; e < 16; ++e) w[e / 4] |= ((y[e] >> shift) & 255u) << (8 * (e % 4));
+    // digit = byte - 128: flip the top bit of every byte
+    *reinterpret_cast<uint4 *>(dst) =
+        make_uint4(w[0] ^ 0x80808080u, w[1] ^ 0x80808080u, w[2] ^ 0x80808080u, w[3] ^ 0x80808080u);
+}
+
+// One thread per (j, 16-coefficient chunk c, gate g).
+__global__ void mfma_rotdec_kernel(MfmaArgs a, int step) {
+    const int N = a.N, K1 = a.k + 1, NC = N / 16;
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t total = (size_t)K1 * NC * a.GP;
+    if (idx >= total) return;
+    const int g = (int)(idx % a.GP);
+    const int c = (int)((idx / a.GP) % NC);
+    const int j = (int)(idx / ((size_t)a.GP * NC));
+    const int shift = g < a.G ? (int)a.abar[(size_t)g * (a.k * a.n + 1) + 1 + step] : 0;
+    const uint32_t *row = a.acc + ((size_t)g * K1 + j) * N;
+    uint32_t y[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int m = 16 * c + e;
+        const int s = m + shift;
+        const uint32_t src = row[s & (N - 1)];
+        const uint32_t rot = ((s >> a.log2N) & 1) ? 0u - src : src;
+        y[e] = rot - row[m] + a.offset;
+    }
+    const int GT = a.GP / 32, NB = N / 32;
+    const int gt = g / 32, lane = (c & 1) * 32 + (g & 31), kb = c >> 1;
+    for (int l = 0; l < a.ell; ++l) {
+        int8_t *dst = a.U + ((((size_t)(j * a.ell + l) * GT + gt) * NB + kb) * 64 + lane) * 16;
+        store_digits16(dst, y, 24 - 8 * l);
+    }
+    if (j == 0) {
+        uint4 *w = reinterpret_cast<uint4 *>(a.W + (size_t)g * N + 16 * c);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w[q] = make_uint4(0, 0, 0, 0);
+    }
+}
+
+// One thread per (16-coefficient chunk c, gate g): V = g^-1(W).
+__global__ void mfma_wdec_kernel(MfmaArgs a) {
+    const int N = a.N, NC = N / 16;
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t total = (size_t)NC * a.GP;
+    if (idx >= total) return;
+    const int g = (int)(idx % a.GP);
+    const int c = (int)(idx / a.GP);
+    const uint4 *src = reinterpret_cast<const uint4 *>(a.W + (size_t)g * N + 16 * c);
+    uint32_t y[16];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint4 x = src[q];
+        y[4 * q + 0] = x.x + a.offset;
+        y[4 * q + 1] = x.y + a.offset;
+        y[4 * q + 2] = x.z + a.offset;
+        y[4 * q + 3] = x.w + a.offset;
+    }
+    const int GT = a.GP / 32, NB = N / 32;
+    const int gt = g / 32, lane = (c & 1) * 32 + (g & 31), kb = c >> 1;
+    for (int l = 0; l < a.ell; ++l) {
+        int8_t *dst = a.V + ((((size_t)l * GT + gt) * NB + kb) * 64 + lane) * 16;
+        store_digits16(dst, y, 24 - 8 * l);
+    }
+}
+
+template <int MR>
+__device__ __forceinline__ void toeplitz_gemm(const int8_t *__restrict__ Apoly,  // [4][ND][1024]
+                                              const int8_t *__restrict__ Bpoly,  // [NB][1024]
+                                              int NB, int mb0, int lane, v16i (&acc)[MR][4]) {
+    const int ND = 2 * NB - 1;
+    for (int kb = 0; kb < NB; ++kb) {
+        const v4i b = *reinterpret_cast<const v4i *>(Bpoly + (size_t)kb * kTileBytes + lane * 16);
+#pragma unroll
+        for (int r = 0; r < MR; ++r) {
+            const int d = mb0 + r - kb + NB - 1;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const v4i av = *reinterpret_cast<const v4i *>(
+                    Apoly + ((size_t)t * ND + d) * kTileBytes + lane * 16);
+                acc[r][t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(av, b, acc[r][t], 0, 0, 0);
+            }
+        }
+    }
+}
+
+// Recombines the limbs of output register e of row tile r.
+template <int MR>
+__device__ __forceinline__ uint32_t combine(const v16i (&acc)[MR][4], int r, int e) {
+    return (uint32_t)acc[r][0][e] + ((uint32_t)acc[r][1][e] << 8) +
+           ((uint32_t)acc[r][2][e] << 16) + ((uint32_t)acc[r][3][e] << 24);
+}
+
+constexpr int kMR1 = 4;  // row tiles per wave in stage 1
+constexpr int kMR2 = 2;  // row tiles per wave in stage 2
+
+// Stage 1.  Item = (kind, j, row block rb, gate tile gt), one wave each:
+// kind 0 adds c'_j into ACC_j, kind 1 adds w_j into W.
+__global__ __launch_bounds__(64) void mfma_gemm1_kernel(MfmaArgs a, int party, int bit) {
+    const int N = a.N, NB = N / 32, ND = 2 * NB - 1, K1 = a.k + 1, ell = a.ell;
+    const int RB = NB / kMR1, GT = a.GP / 32;
+    const int lane = threadIdx.x;
+    size_t item = blockIdx.x;
+    const int gt = (int)(item % GT);
+    item /= GT;
+    const int rb = (int)(item % RB);
+    item /= RB;
+    const int j = (int)(item % K1);
+    const int kind = (int)(item / K1);
+    v16i acc[kMR1][4];
+#pragma unroll
+    for (int r = 0; r < kMR1; ++r)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[r][t] = v16i{};
+    const size_t poly_tiles = (size_t)4 * ND * kTileBytes;
+    for (int l = 0; l < ell; ++l) {
+        const int8_t *A = kind == 0
+            ? a.bk + ((((size_t)party * a.n + bit) * 3 + 0) * ell + l) * poly_tiles
+            : a.evk + ((size_t)j * ell + l) * poly_tiles;
+        const int8_t *B = a.U + ((size_t)(j * ell + l) * GT + gt) * NB * kTileBytes;
+        toeplitz_gemm<kMR1>(A, B, NB, rb * kMR1, lane, acc);
+    }
+    const int g = gt * 32 + (lane & 31);
+#pragma unroll
+    for (int r = 0; r < kMR1; ++r)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int m = 32 * (rb * kMR1 + r) + 8 * (e / 4) + 4 * (lane / 32) + (e % 4);
+            const uint32_t v = combine<kMR1>(acc, r, e);
+            if (kind == 0)
+                a.acc[((size_t)g * K1 + j) * N + m] += v;
+            else
+                atomicAdd(a.W + (size_t)g * N + m, v);
+        }
+}
+
+// Stage 2.  Item = (o, row block, gate tile): ACC_{o ? 1+party : 0} += T(f_o) V.
+__global__ __launch_bounds__(64) void mfma_gemm2_kernel(MfmaArgs a, int party, int bit) {
+    const int N = a.N, NB = N / 32, ND = 2 * NB - 1, K1 = a.k + 1, ell = a.ell;
+    const int RB = NB / kMR2, GT = a.GP / 32;
+    const int lane = threadIdx.x;
+    size_t item = blockIdx.x;
+    const int gt = (int)(item % GT);
+    item /= GT;
+    const int rb = (int)(item % RB);
+    const int o = (int)(item / RB);
+    v16i acc[kMR2][4];
+#pragma unroll
+    for (int r = 0; r < kMR2; ++r)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[r][t] = v16i{};
+    const size_t poly_tiles = (size_t)4 * ND * kTileBytes;
+    for (int l = 0; l < ell; ++l) {
+        const int8_t *A = a.bk + ((((size_t)party * a.n + bit) * 3 + 1 + o) * ell + l) * poly_tiles;
+        const int8_t *B = a.V + ((size_t)l * GT + gt) * NB * kTileBytes;
+        toeplitz_gemm<kMR2>(A, B, NB, rb * kMR2, lane, acc);
+    }
+    const int g = gt * 32 + (lane & 31);
+    const int jd = o == 0 ? 0 : 1 + party;
+#pragma unroll
+    for (int r = 0; r < kMR2; ++r)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int m = 32 * (rb * kMR2 + r) + 8 * (e / 4) + 4 * (lane / 32) + (e % 4);
+            a.acc[((size_t)g * K1 + jd) * N + m] += combine<kMR2>(acc, r, e);
+        }
+}
+
+__global__ void mfma_copyout_kernel(const uint32_t *__restrict__ src, uint32_t *__restrict__ dst,
+                                    size_t words) {
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < words) dst[idx] = src[idx];
+}
+
+static inline unsigned blocks(size_t threads, int per) { return (unsigned)((threads + per - 1) / per); }
+
+int launch_br_mfma(mk_ctx *ctx, const uint32_t *abar, uint32_t *acc_out, size_t count, int steps,
+                   hipStream_t s) {
+    const mk_params &P = ctx->p;
+    if (P.N < 32 * kMR1) return fail(MK_EPARAM, "int8-MFMA path needs N >= 128");
+    const size_t GP = (count + 31) / 32 * 32;
+    const int K1 = P.k + 1, N = P.N, ell = P.bk_ell;
+    // a scratch region owned by the MFMA path (grown on demand)
+    const size_t acc_b = GP * K1 * N * 4, w_b = GP * N * 4;
+    const size_t u_b = (size_t)K1 * ell * GP * N, v_b = (size_t)ell * GP * N;
+    DeviceKeys &D = ctx->dev;
+    const size_t need = acc_b + w_b + u_b + v_b;
+    if (D.mfma_scratch_bytes < need) {
+        if (D.mfma_scratch) {
+            MK_HIP(hipStreamSynchronize(s), "mfma scratch sync");
+            (void)hipFree(D.mfma_scratch);
+            D.mfma_scratch = nullptr;
+            D.mfma_scratch_bytes = 0;
+        }
+        if (hipMalloc(&D.mfma_scratch, need) != hipSuccess) {
+            D.mfma_scratch = nullptr;
+            return fail(MK_ENOMEM, "device allocation failed: MFMA scratch");
+        }
+        D.mfma_scratch_bytes = need;
+    }
+    char *sp = (char *)D.mfma_scratch;
+    MfmaArgs a;
+    a.k = P.k; a.n = P.n; a.N = N; a.ell = ell; a.log2N = __builtin_ctz(N);
+    a.GP = (int)GP; a.G = (int)count;
+    a.offset = decomp_offset(ell);
+    a.abar = abar;
+    a.acc = (uint32_t *)sp;
+    a.W = (uint32_t *)(sp + acc_b);
+    a.U = (int8_t *)(sp + acc_b + w_b);
+    a.V = (int8_t *)(sp + acc_b + w_b + u_b);
+    a.bk = D.bk_win;
+    a.evk = D.evk_win;
+    const int NB = N / 32, GT = (int)(GP / 32);
+    {
+        StageTimer tm(ctx, 1, s);
+        hipLaunchKernelGGL(mfma_init_kernel, dim3(blocks(GP * K1 * N, 256)), dim3(256), 0, s, a);
+        MK_HIP(hipGetLastError(), "mfma init launch");
+        const unsigned rd_blocks = blocks((size_t)K1 * (N / 16) * GP, 256);
+        const unsigned wd_blocks = blocks((size_t)(N / 16) * GP, 256);
+        const unsigned g1 = (unsigned)(2 * K1 * (NB / kMR1) * GT);
+        const unsigned g2 = (unsigned)(2 * (NB / kMR2) * GT);
+        for (int st = 0; st < steps; ++st) {
+            const int party = st / P.n, bit = st % P.n;
+            {
+                StageTimer t6(ctx, 6, s);
+                hipLaunchKernelGGL(mfma_rotdec_kernel, dim3(rd_blocks), dim3(256), 0, s, a, st);
+            }
+            {
+                StageTimer t4(ctx, 4, s);
+                hipLaunchKernelGGL(mfma_gemm1_kernel, dim3(g1), dim3(64), 0, s, a, party, bit);
+            }
+            {
+                StageTimer t7(ctx, 7, s);
+                hipLaunchKernelGGL(mfma_wdec_kernel, dim3(wd_blocks), dim3(256), 0, s, a);
+            }
+            {
+                StageTimer t5(ctx, 5, s);
+                hipLaunchKernelGGL(mfma_gemm2_kernel, dim3(g2), dim3(64), 0, s, a, party, bit);
+            }
+        }
+        MK_HIP(hipGetLastError(), "mfma step launch");
+        hipLaunchKernelGGL(mfma_copyout_kernel, dim3(blocks(count * K1 * N, 256)), dim3(256), 0, s,
+                           a.acc, acc_out, count * K1 * N);
+        MK_HIP(hipGetLastError(), "mfma copyout launch");
+    }
+    return MK_OK;
 }
 
 }  // namespace mk

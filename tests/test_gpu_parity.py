@@ -10,7 +10,7 @@ from tests import helpers
 
 pytestmark = pytest.mark.gpu
 
-PATHS = [0]   # MK_PATH_I32; the int8-MFMA path joins once built
+PATHS = [0, 1]   # MK_PATH_I32, MK_PATH_MFMA_I8
 
 
 @pytest.fixture(scope="module")
