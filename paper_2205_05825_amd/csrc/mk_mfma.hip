@@ -21,14 +21,14 @@
 //
 // Per CMux step (party i, bit l) four kernels run:
 //   rotdec : P_j = X^-a ACC_j - ACC_j per gate, decomposed into ell int8
-//            digit polynomials stored as MFMA B fragments; clears W.
-//   gemm1  : for every (unit, 128-row block, 32-gate tile): unit c'_j adds
-//            sum_l T(d_l) U_{j,l} into ACC_j; unit w_j adds
-//            sum_l T(b_{j,l}) U_{j,l} into W with wrapping atomics.
-//   wdec   : V = g^-1(W) as B fragments.
+//            digit polynomials stored as MFMA B fragments.
+//   gemm1  : for every (unit, 64-row block, 32-gate tile): unit c'_j adds
+//            sum_l T(d_l) U_{j,l} into ACC_j; unit w_j writes the partial
+//            sum_l T(b_{j,l}) U_{j,l} to W_j.
+//   wdec   : V = g^-1(sum_j W_j) as B fragments.
 //   gemm2  : ACC_0 += sum_l T(f0_l) V_l ;  ACC_{1+i} += sum_l T(f1_l) V_l.
 // Layouts (GP = gates padded to 32, GT = GP/32, NB = N/32, ND = 2 NB - 1):
-//   acc  u32 [GP][k+1][N]                 W  u32 [GP][N]
+//   acc  u32 [GP][k+1][N]                 W  u32 [k+1][GP][N]
 //   U    i8  [k+1][ell][GT][NB][64][16]    V  i8  [ell][GT][NB][64][16]
 //   bk   i8  [k][n][3][ell][4][ND][64][16]
 //   evk  i8  [k+1][ell][4][ND][64][16]
@@ -119,7 +119,7 @@ struct MfmaArgs {
     uint32_t offset;          // gadget decomposition offset
     const uint32_t *abar;     // [G][kn+1]
     uint32_t *acc;            // [GP][k+1][N]
-    uint32_t *W;              // [GP][N]
+    uint32_t *W;              // [k+1][GP][N] partial sums w_j
     int8_t *U;                // [k+1][ell][GT][NB][64][16]
     int8_t *V;                // [ell][GT][NB][64][16]
     const int8_t *bk;         // [k][n][3][ell][4][ND][1024]
@@ -179,11 +179,6 @@ __global__ void mfma_rotdec_kernel(MfmaArgs a, int step) {
         int8_t *dst = a.U + ((((size_t)(j * a.ell + l) * GT + gt) * NB + kb) * 64 + lane) * 16;
         store_digits16(dst, y, 24 - 8 * l);
     }
-    if (j == 0) {
-        uint4 *w = reinterpret_cast<uint4 *>(a.W + (size_t)g * N + 16 * c);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) w[q] = make_uint4(0, 0, 0, 0);
-    }
 }
 
 // One thread per (16-coefficient chunk c, gate g): V = g^-1(W).
@@ -194,15 +189,19 @@ __global__ void mfma_wdec_kernel(MfmaArgs a) {
     if (idx >= total) return;
     const int g = (int)(idx % a.GP);
     const int c = (int)(idx / a.GP);
-    const uint4 *src = reinterpret_cast<const uint4 *>(a.W + (size_t)g * N + 16 * c);
     uint32_t y[16];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const uint4 x = src[q];
-        y[4 * q + 0] = x.x + a.offset;
-        y[4 * q + 1] = x.y + a.offset;
-        y[4 * q + 2] = x.z + a.offset;
-        y[4 * q + 3] = x.w + a.offset;
+    for (int e = 0; e < 16; ++e) y[e] = a.offset;
+    for (int j = 0; j <= a.k; ++j) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(a.W + ((size_t)j * a.GP + g) * N + 16 * c);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint4 x = src[q];
+            y[4 * q + 0] += x.x;
+            y[4 * q + 1] += x.y;
+            y[4 * q + 2] += x.z;
+            y[4 * q + 3] += x.w;
+        }
     }
     const int GT = a.GP / 32, NB = N / 32;
     const int gt = g / 32, lane = (c & 1) * 32 + (g & 31), kb = c >> 1;
@@ -212,23 +211,48 @@ __global__ void mfma_wdec_kernel(MfmaArgs a) {
     }
 }
 
+// Accumulates acc[r][t] += T_t(A)[rows of tile mb0+r] * B over all NB
+// K-blocks, for the 4 limbs t.  The Toeplitz tile of (row tile mb, K-block
+// kb) is diagonal tile mb - kb, so when kb advances every row tile inherits
+// the previous tile of the row tile above it and only row tile 0 needs a new
+// one: a register window of MR tiles per limb, one new tile per limb per
+// K-block.  The next K-block's tiles are prefetched before the MFMAs.
 template <int MR>
-__device__ __forceinline__ void toeplitz_gemm(const int8_t *__restrict__ Apoly,  // [4][ND][1024]
-                                              const int8_t *__restrict__ Bpoly,  // [NB][1024]
+__device__ __forceinline__ void toeplitz_gemm(const int8_t *__restrict__ A,  // [4][ND][1024]
+                                              const int8_t *__restrict__ B,  // [NB][1024]
                                               int NB, int mb0, int lane, v16i (&acc)[MR][4]) {
     const int ND = 2 * NB - 1;
+    const int8_t *Al = A + lane * 16;
+    const int8_t *Bl = B + lane * 16;
+    v4i win[MR][4];
+#pragma unroll
+    for (int r = 0; r < MR; ++r)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            win[r][t] = *reinterpret_cast<const v4i *>(
+                Al + ((size_t)t * ND + mb0 + r + NB - 1) * kTileBytes);
+    v4i b = *reinterpret_cast<const v4i *>(Bl);
     for (int kb = 0; kb < NB; ++kb) {
-        const v4i b = *reinterpret_cast<const v4i *>(Bpoly + (size_t)kb * kTileBytes + lane * 16);
+        // prefetch K-block kb+1 (clamped in range on the last iteration)
+        const int kn = kb + 1 < NB ? kb + 1 : kb;
+        const int dn = mb0 - kn + NB - 1;
+        const v4i nb = *reinterpret_cast<const v4i *>(Bl + (size_t)kn * kTileBytes);
+        v4i nw[4];
 #pragma unroll
-        for (int r = 0; r < MR; ++r) {
-            const int d = mb0 + r - kb + NB - 1;
+        for (int t = 0; t < 4; ++t)
+            nw[t] = *reinterpret_cast<const v4i *>(Al + ((size_t)t * ND + dn) * kTileBytes);
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const v4i av = *reinterpret_cast<const v4i *>(
-                    Apoly + ((size_t)t * ND + d) * kTileBytes + lane * 16);
-                acc[r][t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(av, b, acc[r][t], 0, 0, 0);
-            }
+        for (int r = 0; r < MR; ++r)
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                acc[r][t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(win[r][t], b, acc[r][t], 0, 0, 0);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+#pragma unroll
+            for (int r = MR - 1; r > 0; --r) win[r][t] = win[r - 1][t];
+            win[0][t] = nw[t];
         }
+        b = nb;
     }
 }
 
@@ -239,25 +263,40 @@ __device__ __forceinline__ uint32_t combine(const v16i (&acc)[MR][4], int r, int
            ((uint32_t)acc[r][2][e] << 16) + ((uint32_t)acc[r][3][e] << 24);
 }
 
-constexpr int kMR1 = 4;  // row tiles per wave in stage 1
-constexpr int kMR2 = 2;  // row tiles per wave in stage 2
+constexpr int kMR = 2;      // row tiles (of 32) per wave
+constexpr int kWaves = 4;   // waves per workgroup, one 32-gate tile each
 
-// Stage 1.  Item = (kind, j, row block rb, gate tile gt), one wave each:
-// kind 0 adds c'_j into ACC_j, kind 1 adds w_j into W.
-__global__ __launch_bounds__(64) void mfma_gemm1_kernel(MfmaArgs a, int party, int bit) {
+// Task decode shared by both GEMMs: the gate group (kWaves gate tiles) is the
+// fastest index, so with 8 gate groups each XCD keeps one group's digits in
+// its L2, while the key tiles of a (unit, row block) are shared by the four
+// waves of a workgroup through the CU's L1.
+struct Task {
+    int unit, rb, gt;
+};
+__device__ __forceinline__ Task decode_task(int GT, int RB) {
+    const int GG = (GT + kWaves - 1) / kWaves;
+    int task = blockIdx.x;
+    Task t;
+    const int gg = task % GG;
+    task /= GG;
+    t.rb = task % RB;
+    t.unit = task / RB;
+    t.gt = gg * kWaves + (int)(threadIdx.x / 64);
+    return t;
+}
+
+// Stage 1.  Unit u < k+1 adds c'_u = sum_l T(d_l) U_{u,l} into ACC_u; unit
+// u = k+1+j writes the partial w_j = sum_l T(b_{j,l}) U_{j,l} to Wp[j].
+__global__ __launch_bounds__(256, 2) void mfma_gemm1_kernel(MfmaArgs a, int party, int bit) {
     const int N = a.N, NB = N / 32, ND = 2 * NB - 1, K1 = a.k + 1, ell = a.ell;
-    const int RB = NB / kMR1, GT = a.GP / 32;
-    const int lane = threadIdx.x;
-    size_t item = blockIdx.x;
-    const int gt = (int)(item % GT);
-    item /= GT;
-    const int rb = (int)(item % RB);
-    item /= RB;
-    const int j = (int)(item % K1);
-    const int kind = (int)(item / K1);
-    v16i acc[kMR1][4];
+    const int GT = a.GP / 32;
+    const Task tk = decode_task(GT, NB / kMR);
+    if (tk.gt >= GT) return;
+    const int lane = threadIdx.x & 63;
+    const int kind = tk.unit / K1, j = tk.unit % K1;
+    v16i acc[kMR][4];
 #pragma unroll
-    for (int r = 0; r < kMR1; ++r)
+    for (int r = 0; r < kMR; ++r)
 #pragma unroll
         for (int t = 0; t < 4; ++t) acc[r][t] = v16i{};
     const size_t poly_tiles = (size_t)4 * ND * kTileBytes;
@@ -265,52 +304,62 @@ __global__ __launch_bounds__(64) void mfma_gemm1_kernel(MfmaArgs a, int party, i
         const int8_t *A = kind == 0
             ? a.bk + ((((size_t)party * a.n + bit) * 3 + 0) * ell + l) * poly_tiles
             : a.evk + ((size_t)j * ell + l) * poly_tiles;
-        const int8_t *B = a.U + ((size_t)(j * ell + l) * GT + gt) * NB * kTileBytes;
-        toeplitz_gemm<kMR1>(A, B, NB, rb * kMR1, lane, acc);
+        const int8_t *B = a.U + ((size_t)(j * ell + l) * GT + tk.gt) * NB * kTileBytes;
+        toeplitz_gemm<kMR>(A, B, NB, tk.rb * kMR, lane, acc);
     }
-    const int g = gt * 32 + (lane & 31);
+    const int g = tk.gt * 32 + (lane & 31);
+    uint32_t *dst = kind == 0 ? a.acc + ((size_t)g * K1 + j) * N
+                              : a.W + ((size_t)j * a.GP + g) * N;
 #pragma unroll
-    for (int r = 0; r < kMR1; ++r)
+    for (int r = 0; r < kMR; ++r)
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const int m = 32 * (rb * kMR1 + r) + 8 * (e / 4) + 4 * (lane / 32) + (e % 4);
-            const uint32_t v = combine<kMR1>(acc, r, e);
-            if (kind == 0)
-                a.acc[((size_t)g * K1 + j) * N + m] += v;
-            else
-                atomicAdd(a.W + (size_t)g * N + m, v);
+        for (int q = 0; q < 4; ++q) {
+            // registers 4q..4q+3 hold 4 consecutive rows of one column
+            const int m = 32 * (tk.rb * kMR + r) + 8 * q + 4 * (lane / 32);
+            uint4 *p = reinterpret_cast<uint4 *>(dst + m);
+            uint4 v = make_uint4(combine<kMR>(acc, r, 4 * q + 0), combine<kMR>(acc, r, 4 * q + 1),
+                                 combine<kMR>(acc, r, 4 * q + 2), combine<kMR>(acc, r, 4 * q + 3));
+            if (kind == 0) {
+                const uint4 o = *p;
+                v.x += o.x; v.y += o.y; v.z += o.z; v.w += o.w;
+            }
+            *p = v;
         }
 }
 
-// Stage 2.  Item = (o, row block, gate tile): ACC_{o ? 1+party : 0} += T(f_o) V.
-__global__ __launch_bounds__(64) void mfma_gemm2_kernel(MfmaArgs a, int party, int bit) {
+// Stage 2.  Unit o: ACC_{o ? 1+party : 0} += sum_l T(f_o,l) V_l.
+__global__ __launch_bounds__(256, 2) void mfma_gemm2_kernel(MfmaArgs a, int party, int bit) {
     const int N = a.N, NB = N / 32, ND = 2 * NB - 1, K1 = a.k + 1, ell = a.ell;
-    const int RB = NB / kMR2, GT = a.GP / 32;
-    const int lane = threadIdx.x;
-    size_t item = blockIdx.x;
-    const int gt = (int)(item % GT);
-    item /= GT;
-    const int rb = (int)(item % RB);
-    const int o = (int)(item / RB);
-    v16i acc[kMR2][4];
+    const int GT = a.GP / 32;
+    const Task tk = decode_task(GT, NB / kMR);
+    if (tk.gt >= GT) return;
+    const int lane = threadIdx.x & 63;
+    const int o = tk.unit;
+    v16i acc[kMR][4];
 #pragma unroll
-    for (int r = 0; r < kMR2; ++r)
+    for (int r = 0; r < kMR; ++r)
 #pragma unroll
         for (int t = 0; t < 4; ++t) acc[r][t] = v16i{};
     const size_t poly_tiles = (size_t)4 * ND * kTileBytes;
     for (int l = 0; l < ell; ++l) {
         const int8_t *A = a.bk + ((((size_t)party * a.n + bit) * 3 + 1 + o) * ell + l) * poly_tiles;
-        const int8_t *B = a.V + ((size_t)l * GT + gt) * NB * kTileBytes;
-        toeplitz_gemm<kMR2>(A, B, NB, rb * kMR2, lane, acc);
+        const int8_t *B = a.V + ((size_t)l * GT + tk.gt) * NB * kTileBytes;
+        toeplitz_gemm<kMR>(A, B, NB, tk.rb * kMR, lane, acc);
     }
-    const int g = gt * 32 + (lane & 31);
-    const int jd = o == 0 ? 0 : 1 + party;
+    const int g = tk.gt * 32 + (lane & 31);
+    uint32_t *dst = a.acc + ((size_t)g * K1 + (o == 0 ? 0 : 1 + party)) * N;
 #pragma unroll
-    for (int r = 0; r < kMR2; ++r)
+    for (int r = 0; r < kMR; ++r)
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const int m = 32 * (rb * kMR2 + r) + 8 * (e / 4) + 4 * (lane / 32) + (e % 4);
-            a.acc[((size_t)g * K1 + jd) * N + m] += combine<kMR2>(acc, r, e);
+        for (int q = 0; q < 4; ++q) {
+            const int m = 32 * (tk.rb * kMR + r) + 8 * q + 4 * (lane / 32);
+            uint4 *p = reinterpret_cast<uint4 *>(dst + m);
+            uint4 v = *p;
+            v.x += combine<kMR>(acc, r, 4 * q + 0);
+            v.y += combine<kMR>(acc, r, 4 * q + 1);
+            v.z += combine<kMR>(acc, r, 4 * q + 2);
+            v.w += combine<kMR>(acc, r, 4 * q + 3);
+            *p = v;
         }
 }
 
@@ -325,11 +374,11 @@ static inline unsigned blocks(size_t threads, int per) { return (unsigned)((thre
 int launch_br_mfma(mk_ctx *ctx, const uint32_t *abar, uint32_t *acc_out, size_t count, int steps,
                    hipStream_t s) {
     const mk_params &P = ctx->p;
-    if (P.N < 32 * kMR1) return fail(MK_EPARAM, "int8-MFMA path needs N >= 128");
+    if (P.N < 32 * kMR) return fail(MK_EPARAM, "int8-MFMA path needs N >= 64");
     const size_t GP = (count + 31) / 32 * 32;
     const int K1 = P.k + 1, N = P.N, ell = P.bk_ell;
     // a scratch region owned by the MFMA path (grown on demand)
-    const size_t acc_b = GP * K1 * N * 4, w_b = GP * N * 4;
+    const size_t acc_b = GP * K1 * N * 4, w_b = (size_t)K1 * GP * N * 4;
     const size_t u_b = (size_t)K1 * ell * GP * N, v_b = (size_t)ell * GP * N;
     DeviceKeys &D = ctx->dev;
     const size_t need = acc_b + w_b + u_b + v_b;
@@ -365,8 +414,9 @@ int launch_br_mfma(mk_ctx *ctx, const uint32_t *abar, uint32_t *acc_out, size_t 
         MK_HIP(hipGetLastError(), "mfma init launch");
         const unsigned rd_blocks = blocks((size_t)K1 * (N / 16) * GP, 256);
         const unsigned wd_blocks = blocks((size_t)(N / 16) * GP, 256);
-        const unsigned g1 = (unsigned)(2 * K1 * (NB / kMR1) * GT);
-        const unsigned g2 = (unsigned)(2 * (NB / kMR2) * GT);
+        const int GG = (GT + kWaves - 1) / kWaves;
+        const unsigned g1 = (unsigned)(2 * K1 * (NB / kMR) * GG);
+        const unsigned g2 = (unsigned)(2 * (NB / kMR) * GG);
         for (int st = 0; st < steps; ++st) {
             const int party = st / P.n, bit = st % P.n;
             {
@@ -375,7 +425,7 @@ int launch_br_mfma(mk_ctx *ctx, const uint32_t *abar, uint32_t *acc_out, size_t 
             }
             {
                 StageTimer t4(ctx, 4, s);
-                hipLaunchKernelGGL(mfma_gemm1_kernel, dim3(g1), dim3(64), 0, s, a, party, bit);
+                hipLaunchKernelGGL(mfma_gemm1_kernel, dim3(g1), dim3(64 * kWaves), 0, s, a, party, bit);
             }
             {
                 StageTimer t7(ctx, 7, s);
@@ -383,7 +433,7 @@ int launch_br_mfma(mk_ctx *ctx, const uint32_t *abar, uint32_t *acc_out, size_t 
             }
             {
                 StageTimer t5(ctx, 5, s);
-                hipLaunchKernelGGL(mfma_gemm2_kernel, dim3(g2), dim3(64), 0, s, a, party, bit);
+                hipLaunchKernelGGL(mfma_gemm2_kernel, dim3(g2), dim3(64 * kWaves), 0, s, a, party, bit);
             }
         }
         MK_HIP(hipGetLastError(), "mfma step launch");
