@@ -144,71 +144,102 @@ __global__ void mfma_init_kernel(MfmaArgs a) {
     a.acc[idx] = v;
 }
 
-__device__ __forceinline__ void store_digits16(int8_t *dst, const uint32_t (&y)[16], int shift) {
-    uint32_t w[4] = {0, 0, 0, 0};
-#pragma unroll
-    for (int e = 0; e < 16; ++e) w[e / 4] |= ((y[e] >> shift) & 255u) << (8 * (e % 4));
-    // digit = byte - 128: flip the top bit of every byte
-    *reinterpret_cast<uint4 *>(dst) =
-        make_uint4(w[0] ^ 0x80808080u, w[1] ^ 0x80808080u, w[2] ^ 0x80808080u, w[3] ^ 0x80808080u);
+// Digit kernels.  A workgroup of 256 threads (4 waves) owns one 32-gate tile
+// and a range of kDigKB K-blocks (32 kDigKB coefficients).  Phase 1: wave w
+// handles gates w, w+4, .., w+28 and lane L the coefficients m0 + L + 64 q,
+// so every load instruction reads 64 consecutive words of one gate's row and
+// all 8 gates' loads are in flight together; the ell digit bytes go to LDS
+// as [l][gate][coefficient] (rows padded by 16 bytes against bank
+// conflicts).  Phase 2 writes whole 1 KB MFMA B fragments (lane L = 32 h +
+// gate, 16 bytes = coefficients 32 kb + 16 h ..).
+constexpr int kDigKB = 4;
+constexpr int kDigCoef = 32 * kDigKB;          // coefficients per workgroup
+constexpr int kDigRow = kDigCoef + 16;          // padded LDS row (bytes)
+constexpr int kDigQ = kDigCoef / 64;            // coefficients per lane per gate
+
+__device__ __forceinline__ void digits_to_lds(int8_t *lds, int ell, int g, int mm, uint32_t y) {
+    for (int l = 0; l < ell; ++l)
+        lds[(l * 32 + g) * kDigRow + mm] = (int8_t)((int)((y >> (24 - 8 * l)) & 255u) - 128);
 }
 
-// One thread per (j, 16-coefficient chunk c, gate g).
-__global__ void mfma_rotdec_kernel(MfmaArgs a, int step) {
-    const int N = a.N, K1 = a.k + 1, NC = N / 16;
-    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const size_t total = (size_t)K1 * NC * a.GP;
-    if (idx >= total) return;
-    const int g = (int)(idx % a.GP);
-    const int c = (int)((idx / a.GP) % NC);
-    const int j = (int)(idx / ((size_t)a.GP * NC));
-    const int shift = g < a.G ? (int)a.abar[(size_t)g * (a.k * a.n + 1) + 1 + step] : 0;
-    const uint32_t *row = a.acc + ((size_t)g * K1 + j) * N;
-    uint32_t y[16];
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const int m = 16 * c + e;
-        const int s = m + shift;
-        const uint32_t src = row[s & (N - 1)];
-        const uint32_t rot = ((s >> a.log2N) & 1) ? 0u - src : src;
-        y[e] = rot - row[m] + a.offset;
-    }
-    const int GT = a.GP / 32, NB = N / 32;
-    const int gt = g / 32, lane = (c & 1) * 32 + (g & 31), kb = c >> 1;
-    for (int l = 0; l < a.ell; ++l) {
-        int8_t *dst = a.U + ((((size_t)(j * a.ell + l) * GT + gt) * NB + kb) * 64 + lane) * 16;
-        store_digits16(dst, y, 24 - 8 * l);
+__device__ __forceinline__ void lds_to_frags(const int8_t *lds, int ell, int8_t *dst_l0,
+                                             size_t l_stride, int kb0) {
+    // fragment (l, kb) lives at dst_l0 + l * l_stride + kb * 1024
+    const int tid = threadIdx.x;
+    const int nfr = ell * kDigKB;
+    for (int f = tid / 64; f < nfr; f += 4) {
+        const int l = f / kDigKB, kk = f % kDigKB;
+        const int L = tid & 63, g = L & 31, h = L >> 5;
+        const uint4 v = *reinterpret_cast<const uint4 *>(lds + (l * 32 + g) * kDigRow + 32 * kk + 16 * h);
+        *reinterpret_cast<uint4 *>(dst_l0 + l * l_stride + (size_t)(kb0 + kk) * kTileBytes + L * 16) = v;
     }
 }
 
-// One thread per (16-coefficient chunk c, gate g): V = g^-1(W).
-__global__ void mfma_wdec_kernel(MfmaArgs a) {
-    const int N = a.N, NC = N / 16;
-    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const size_t total = (size_t)NC * a.GP;
-    if (idx >= total) return;
-    const int g = (int)(idx % a.GP);
-    const int c = (int)(idx / a.GP);
-    uint32_t y[16];
+// rotdec: item (j, gate tile, K-block group); P_j = X^-a ACC_j - ACC_j.
+__global__ __launch_bounds__(256) void mfma_rotdec_kernel(MfmaArgs a, int step) {
+    __shared__ __align__(16) int8_t lds[3 * 32 * kDigRow];  // ell <= 3 (ell*8 <= 30)
+    const int N = a.N, K1 = a.k + 1, NB = N / 32, GT = a.GP / 32, KG = NB / kDigKB;
+    int item = blockIdx.x;
+    const int kg = item % KG;
+    item /= KG;
+    const int gt = item % GT;
+    const int j = item / GT;
+    const int m0 = kg * kDigCoef;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int stride = a.k * a.n + 1;
+    uint32_t y[8][kDigQ];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) y[e] = a.offset;
-    for (int j = 0; j <= a.k; ++j) {
-        const uint4 *src = reinterpret_cast<const uint4 *>(a.W + ((size_t)j * a.GP + g) * N + 16 * c);
+    for (int i = 0; i < 8; ++i) {
+        const int g = wave + 4 * i, gg = gt * 32 + g;
+        const int shift = gg < a.G ? (int)a.abar[(size_t)gg * stride + 1 + step] : 0;
+        const uint32_t *row = a.acc + ((size_t)gg * K1 + j) * N;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const uint4 x = src[q];
-            y[4 * q + 0] += x.x;
-            y[4 * q + 1] += x.y;
-            y[4 * q + 2] += x.z;
-            y[4 * q + 3] += x.w;
+        for (int q = 0; q < kDigQ; ++q) {
+            const int m = m0 + lane + 64 * q;
+            const int s = m + shift;
+            const uint32_t src = row[s & (N - 1)];
+            const uint32_t rot = ((s >> a.log2N) & 1) ? 0u - src : src;
+            y[i][q] = rot - row[m] + a.offset;
         }
     }
-    const int GT = a.GP / 32, NB = N / 32;
-    const int gt = g / 32, lane = (c & 1) * 32 + (g & 31), kb = c >> 1;
-    for (int l = 0; l < a.ell; ++l) {
-        int8_t *dst = a.V + ((((size_t)l * GT + gt) * NB + kb) * 64 + lane) * 16;
-        store_digits16(dst, y, 24 - 8 * l);
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int q = 0; q < kDigQ; ++q) digits_to_lds(lds, a.ell, wave + 4 * i, lane + 64 * q, y[i][q]);
+    __syncthreads();
+    lds_to_frags(lds, a.ell, a.U + ((size_t)j * a.ell * GT + gt) * NB * kTileBytes,
+                 (size_t)GT * NB * kTileBytes, kg * kDigKB);
+}
+
+// wdec: item (gate tile, K-block group); V = g^-1(sum_j W_j).
+__global__ __launch_bounds__(256) void mfma_wdec_kernel(MfmaArgs a) {
+    __shared__ __align__(16) int8_t lds[3 * 32 * kDigRow];
+    const int N = a.N, NB = N / 32, GT = a.GP / 32, KG = NB / kDigKB;
+    const int kg = blockIdx.x % KG;
+    const int gt = blockIdx.x / KG;
+    const int m0 = kg * kDigCoef;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    uint32_t y[8][kDigQ];
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int q = 0; q < kDigQ; ++q) y[i][q] = a.offset;
+    for (int j = 0; j <= a.k; ++j) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int gg = gt * 32 + wave + 4 * i;
+            const uint32_t *row = a.W + ((size_t)j * a.GP + gg) * N + m0 + lane;
+#pragma unroll
+            for (int q = 0; q < kDigQ; ++q) y[i][q] += row[64 * q];
+        }
     }
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int q = 0; q < kDigQ; ++q) digits_to_lds(lds, a.ell, wave + 4 * i, lane + 64 * q, y[i][q]);
+    __syncthreads();
+    lds_to_frags(lds, a.ell, a.V + (size_t)gt * NB * kTileBytes, (size_t)GT * NB * kTileBytes,
+                 kg * kDigKB);
 }
 
 // Accumulates acc[r][t] += T_t(A)[rows of tile mb0+r] * B over all NB
@@ -216,7 +247,8 @@ __global__ void mfma_wdec_kernel(MfmaArgs a) {
 // kb) is diagonal tile mb - kb, so when kb advances every row tile inherits
 // the previous tile of the row tile above it and only row tile 0 needs a new
 // one: a register window of MR tiles per limb, one new tile per limb per
-// K-block.  The next K-block's tiles are prefetched before the MFMAs.
+// K-block.  Loads run two K-blocks ahead of the MFMAs (a two-slot ring,
+// unrolled so that every register index is static).
 template <int MR>
 __device__ __forceinline__ void toeplitz_gemm(const int8_t *__restrict__ A,  // [4][ND][1024]
                                               const int8_t *__restrict__ B,  // [NB][1024]
@@ -224,6 +256,10 @@ __device__ __forceinline__ void toeplitz_gemm(const int8_t *__restrict__ A,  // 
     const int ND = 2 * NB - 1;
     const int8_t *Al = A + lane * 16;
     const int8_t *Bl = B + lane * 16;
+    auto ldA = [&](int t, int kb) {
+        return *reinterpret_cast<const v4i *>(Al + ((size_t)t * ND + mb0 - kb + NB - 1) * kTileBytes);
+    };
+    auto ldB = [&](int kb) { return *reinterpret_cast<const v4i *>(Bl + (size_t)kb * kTileBytes); };
     v4i win[MR][4];
 #pragma unroll
     for (int r = 0; r < MR; ++r)
@@ -231,16 +267,20 @@ __device__ __forceinline__ void toeplitz_gemm(const int8_t *__restrict__ A,  // 
         for (int t = 0; t < 4; ++t)
             win[r][t] = *reinterpret_cast<const v4i *>(
                 Al + ((size_t)t * ND + mb0 + r + NB - 1) * kTileBytes);
-    v4i b = *reinterpret_cast<const v4i *>(Bl);
-    for (int kb = 0; kb < NB; ++kb) {
-        // prefetch K-block kb+1 (clamped in range on the last iteration)
-        const int kn = kb + 1 < NB ? kb + 1 : kb;
-        const int dn = mb0 - kn + NB - 1;
-        const v4i nb = *reinterpret_cast<const v4i *>(Bl + (size_t)kn * kTileBytes);
-        v4i nw[4];
+    v4i b = ldB(0);
+    // ring slot s holds the new tiles of K-block kb+1 (s = kb & 1)
+    v4i pa0[4], pa1[4], pb0, pb1;
+    {
+        const int k1 = NB > 1 ? 1 : 0, k2 = NB > 2 ? 2 : NB - 1;
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
-            nw[t] = *reinterpret_cast<const v4i *>(Al + ((size_t)t * ND + dn) * kTileBytes);
+        for (int t = 0; t < 4; ++t) {
+            pa0[t] = ldA(t, k1);
+            pa1[t] = ldA(t, k2);
+        }
+        pb0 = ldB(k1);
+        pb1 = ldB(k2);
+    }
+    auto step = [&](int kb, v4i (&pa)[4], v4i &pb) {
 #pragma unroll
         for (int r = 0; r < MR; ++r)
 #pragma unroll
@@ -250,9 +290,17 @@ __device__ __forceinline__ void toeplitz_gemm(const int8_t *__restrict__ A,  // 
         for (int t = 0; t < 4; ++t) {
 #pragma unroll
             for (int r = MR - 1; r > 0; --r) win[r][t] = win[r - 1][t];
-            win[0][t] = nw[t];
+            win[0][t] = pa[t];
         }
-        b = nb;
+        b = pb;
+        const int kf = kb + 3 < NB ? kb + 3 : NB - 1;  // clamped: stays in range
+#pragma unroll
+        for (int t = 0; t < 4; ++t) pa[t] = ldA(t, kf);
+        pb = ldB(kf);
+    };
+    for (int kb = 0; kb < NB; kb += 2) {  // NB is even (N >= 64)
+        step(kb, pa0, pb0);
+        step(kb + 1, pa1, pb1);
     }
 }
 
@@ -374,7 +422,7 @@ static inline unsigned blocks(size_t threads, int per) { return (unsigned)((thre
 int launch_br_mfma(mk_ctx *ctx, const uint32_t *abar, uint32_t *acc_out, size_t count, int steps,
                    hipStream_t s) {
     const mk_params &P = ctx->p;
-    if (P.N < 32 * kMR) return fail(MK_EPARAM, "int8-MFMA path needs N >= 64");
+    if (P.N < kDigCoef) return fail(MK_EPARAM, "int8-MFMA path needs N >= 128");
     const size_t GP = (count + 31) / 32 * 32;
     const int K1 = P.k + 1, N = P.N, ell = P.bk_ell;
     // a scratch region owned by the MFMA path (grown on demand)
@@ -412,8 +460,9 @@ int launch_br_mfma(mk_ctx *ctx, const uint32_t *abar, uint32_t *acc_out, size_t 
         StageTimer tm(ctx, 1, s);
         hipLaunchKernelGGL(mfma_init_kernel, dim3(blocks(GP * K1 * N, 256)), dim3(256), 0, s, a);
         MK_HIP(hipGetLastError(), "mfma init launch");
-        const unsigned rd_blocks = blocks((size_t)K1 * (N / 16) * GP, 256);
-        const unsigned wd_blocks = blocks((size_t)(N / 16) * GP, 256);
+        const int KG = NB / kDigKB;
+        const unsigned rd_blocks = (unsigned)(K1 * GT * KG);
+        const unsigned wd_blocks = (unsigned)(GT * KG);
         const int GG = (GT + kWaves - 1) / kWaves;
         const unsigned g1 = (unsigned)(2 * K1 * (NB / kMR) * GG);
         const unsigned g2 = (unsigned)(2 * (NB / kMR) * GG);
