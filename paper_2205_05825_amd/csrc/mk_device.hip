@@ -291,13 +291,16 @@ __global__ __launch_bounds__(512) void br_plain_kernel(BrPlainArgs a) {
     }
     __syncthreads();
 
-    const int units1 = K1 * (N / kR), units2 = 2 * (N / kR);
+    const int units2 = 2 * (N / kR);
     for (int st = 0; st < a.steps; ++st) {
         const int party = st / a.n, bit = st - party * a.n;
         const int ashift = (int)ab[1 + st];
         if (ashift == 0) continue;  // X^0 ACC - ACC = 0 adds nothing
+        // Slots j >= party+2 are still exactly zero (only c'_0 and c'_{1+i}
+        // receive stage-2 output, and a zero slot has zero digits): skipped.
+        const int live = min(K1, party + 2);
         // 1. rotate, subtract, decompose
-        for (int idx = tid; idx < K1 * N; idx += T) {
+        for (int idx = tid; idx < live * N; idx += T) {
             const int j = idx >> log2N, m = idx & (N - 1);
             const int s = m + ashift;
             const uint32_t src = acc[(j << log2N) + (s & (N - 1))];
@@ -309,7 +312,7 @@ __global__ __launch_bounds__(512) void br_plain_kernel(BrPlainArgs a) {
         __syncthreads();
         const uint32_t *bkbit = a.bk_ext + ((size_t)party * a.n + bit) * 3 * ell * 2 * N;
         // 2. stage 1
-        for (int u = tid; u < units1; u += T) {
+        for (int u = tid; u < live * (N / kR); u += T) {
             const int j = u / (N / kR), m0 = (u - j * (N / kR)) * kR;
             int lo[2][kR] = {}, hi[2][kR] = {};
             for (int l = 0; l < ell; ++l) {
@@ -327,7 +330,7 @@ __global__ __launch_bounds__(512) void br_plain_kernel(BrPlainArgs a) {
         // 3. w = sum_j w_j, decomposed
         for (int m = tid; m < N; m += T) {
             uint32_t w = 0;
-            for (int j = 0; j < K1; ++j) w += wpart[j * N + m];
+            for (int j = 0; j < live; ++j) w += wpart[j * N + m];
             const uint32_t y = w + offset;
             for (int l = 0; l < ell; ++l)
                 vdig[l * N + m] = (int8_t)((int)((y >> (24 - 8 * l)) & 255u) - 128);

@@ -212,7 +212,7 @@ __global__ __launch_bounds__(256) void mfma_rotdec_kernel(MfmaArgs a, int step) 
 }
 
 // wdec: item (gate tile, K-block group); V = g^-1(sum_j W_j).
-__global__ __launch_bounds__(256) void mfma_wdec_kernel(MfmaArgs a) {
+__global__ __launch_bounds__(256) void mfma_wdec_kernel(MfmaArgs a, int live) {
     __shared__ __align__(16) int8_t lds[3 * 32 * kDigRow];
     const int N = a.N, NB = N / 32, GT = a.GP / 32, KG = NB / kDigKB;
     const int kg = blockIdx.x % KG;
@@ -224,7 +224,7 @@ __global__ __launch_bounds__(256) void mfma_wdec_kernel(MfmaArgs a) {
     for (int i = 0; i < 8; ++i)
 #pragma unroll
         for (int q = 0; q < kDigQ; ++q) y[i][q] = a.offset;
-    for (int j = 0; j <= a.k; ++j) {
+    for (int j = 0; j < live; ++j) {
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int gg = gt * 32 + wave + 4 * i;
@@ -333,15 +333,16 @@ __device__ __forceinline__ Task decode_task(int GT, int RB) {
     return t;
 }
 
-// Stage 1.  Unit u < k+1 adds c'_u = sum_l T(d_l) U_{u,l} into ACC_u; unit
-// u = k+1+j writes the partial w_j = sum_l T(b_{j,l}) U_{j,l} to Wp[j].
-__global__ __launch_bounds__(256, 2) void mfma_gemm1_kernel(MfmaArgs a, int party, int bit) {
+// Stage 1.  Unit u < live adds c'_u = sum_l T(d_l) U_{u,l} into ACC_u; unit
+// u = live+j writes the partial w_j = sum_l T(b_{j,l}) U_{j,l} to Wp[j].
+// Slots j >= live are identically zero (see launch_br_mfma) and skipped.
+__global__ __launch_bounds__(256, 2) void mfma_gemm1_kernel(MfmaArgs a, int party, int bit, int live) {
     const int N = a.N, NB = N / 32, ND = 2 * NB - 1, K1 = a.k + 1, ell = a.ell;
     const int GT = a.GP / 32;
     const Task tk = decode_task(GT, NB / kMR);
     if (tk.gt >= GT) return;
     const int lane = threadIdx.x & 63;
-    const int kind = tk.unit / K1, j = tk.unit % K1;
+    const int kind = tk.unit / live, j = tk.unit % live;
     v16i acc[kMR][4];
 #pragma unroll
     for (int r = 0; r < kMR; ++r)
@@ -461,24 +462,29 @@ int launch_br_mfma(mk_ctx *ctx, const uint32_t *abar, uint32_t *acc_out, size_t 
         hipLaunchKernelGGL(mfma_init_kernel, dim3(blocks(GP * K1 * N, 256)), dim3(256), 0, s, a);
         MK_HIP(hipGetLastError(), "mfma init launch");
         const int KG = NB / kDigKB;
-        const unsigned rd_blocks = (unsigned)(K1 * GT * KG);
         const unsigned wd_blocks = (unsigned)(GT * KG);
         const int GG = (GT + kWaves - 1) / kWaves;
-        const unsigned g1 = (unsigned)(2 * K1 * (NB / kMR) * GG);
         const unsigned g2 = (unsigned)(2 * (NB / kMR) * GG);
         for (int st = 0; st < steps; ++st) {
             const int party = st / P.n, bit = st % P.n;
+            // ACC starts as (X^-b v, 0, .., 0) and during party i's steps only
+            // c'_0 and c'_{1+i} receive stage-2 output, while c'_j = 0 whenever
+            // ACC_j = 0 (its digits are all zero).  So slots j >= i+2 are still
+            // exactly zero: their digits, products and partial sums are skipped.
+            const int live = std::min(K1, party + 2);
+            const unsigned rd_blocks = (unsigned)(live * GT * KG);
+            const unsigned g1 = (unsigned)(2 * live * (NB / kMR) * GG);
             {
                 StageTimer t6(ctx, 6, s);
                 hipLaunchKernelGGL(mfma_rotdec_kernel, dim3(rd_blocks), dim3(256), 0, s, a, st);
             }
             {
                 StageTimer t4(ctx, 4, s);
-                hipLaunchKernelGGL(mfma_gemm1_kernel, dim3(g1), dim3(64 * kWaves), 0, s, a, party, bit);
+                hipLaunchKernelGGL(mfma_gemm1_kernel, dim3(g1), dim3(64 * kWaves), 0, s, a, party, bit, live);
             }
             {
                 StageTimer t7(ctx, 7, s);
-                hipLaunchKernelGGL(mfma_wdec_kernel, dim3(wd_blocks), dim3(256), 0, s, a);
+                hipLaunchKernelGGL(mfma_wdec_kernel, dim3(wd_blocks), dim3(256), 0, s, a, live);
             }
             {
                 StageTimer t5(ctx, 5, s);
