@@ -1,0 +1,162 @@
+"""Pins of the oracle's operator netlists: exhaustive plaintext simulation
+against integer arithmetic, gate counts against the paper, the LR netlist
+against its plain-integer definition, and encrypted evaluation at toy shapes
+(CPU only)."""
+import os
+
+import numpy as np
+import pytest
+
+import mk_inputs as mi
+from oracle import circuits as C
+from oracle import lr
+from oracle import params as OP
+from oracle import tfhe
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _all_pairs(k):
+    v = np.arange(-(1 << (k - 1)), 1 << (k - 1))
+    a, b = np.meshgrid(v, v, indexing="ij")
+    return a.ravel(), b.ravel()
+
+
+def _run(nl, k_in, a, b, kb=None):
+    kb = kb or k_in
+    bits = np.concatenate([mi.to_bits(a, k_in).T, mi.to_bits(b, kb).T])
+    return C.eval_plain(nl, bits)
+
+
+def _wrap(v, k):
+    v = np.asarray(v, np.int64) & ((1 << k) - 1)
+    return np.where(v >= 1 << (k - 1), v - (1 << k), v)
+
+
+def _trunc_div(a, b):
+    q = np.abs(a) // np.abs(b) * np.sign(a) * np.sign(b)
+    return q, a - q * b
+
+
+@pytest.mark.parametrize("k", range(1, 9))
+def test_adder_subtractor_exhaustive(k):
+    a, b = _all_pairs(k)
+    add = mi.from_bits(_run(C.adder(k), k, a, b).T)
+    sub = mi.from_bits(_run(C.subtractor(k), k, a, b).T)
+    assert np.array_equal(add, _wrap(a + b, k))
+    assert np.array_equal(sub, _wrap(a - b, k))
+
+
+@pytest.mark.parametrize("k", range(2, 9))
+def test_multiplier_exhaustive(k):
+    a, b = _all_pairs(k)
+    got = mi.from_bits(_run(C.multiplier(k), k, a, b).T)
+    assert np.array_equal(got, a * b)       # 2k-bit product is exact
+
+
+@pytest.mark.parametrize("k", range(2, 9))
+def test_divider_exhaustive(k):
+    a, b = _all_pairs(k)
+    keep = b != 0
+    a, b = a[keep], b[keep]
+    out = _run(C.divider(k), k, a, b)
+    q, r = mi.from_bits(out[:k].T), mi.from_bits(out[k:].T)
+    qe, re = _trunc_div(a, b)
+    assert np.array_equal(q, _wrap(qe, k))   # -2^(k-1) / -1 wraps
+    assert np.array_equal(r, _wrap(re, k))
+
+
+@pytest.mark.parametrize("k", [3, 5])
+def test_divider_double_width_dividend(k):
+    """Paper form (§3.3): 2k-bit dividend, k-bit divisor, small quotients."""
+    rng = np.random.default_rng(k)
+    b = rng.integers(-(1 << (k - 1)), 1 << (k - 1), 3000)
+    b[b == 0] = 1
+    q0 = rng.integers(-(1 << (k - 2)), 1 << (k - 2), 3000)
+    r0 = rng.integers(0, np.abs(b))
+    a = q0 * b + np.where(q0 * b < 0, -r0, r0)
+    out = _run(C.divider(k, 2 * k), 2 * k, a, b, kb=k)
+    q, r = mi.from_bits(out[:k].T), mi.from_bits(out[k:].T)
+    qe, re = _trunc_div(a, b)
+    assert np.array_equal(q, _wrap(qe, k)) and np.array_equal(r, _wrap(re, k))
+
+
+def test_sixteen_bit_operators_random():
+    a, b = mi.operand_pairs(3000, 16, seed=4, nonzero_second=True)
+    assert np.array_equal(mi.from_bits(_run(C.adder(16), 16, a, b).T), _wrap(a + b, 16))
+    assert np.array_equal(mi.from_bits(_run(C.subtractor(16), 16, a, b).T), _wrap(a - b, 16))
+    assert np.array_equal(mi.from_bits(_run(C.multiplier(16), 16, a, b).T), a * b)
+    out = _run(C.divider(16), 16, a, b)
+    qe, re = _trunc_div(a, b)
+    assert np.array_equal(mi.from_bits(out[:16].T), _wrap(qe, 16))
+    assert np.array_equal(mi.from_bits(out[16:].T), _wrap(re, 16))
+
+
+def test_gate_counts_against_paper():
+    """Adder 5k and subtractor 6k as printed (Tables 3 and 5); the multiplier
+    and divider are this design's arrays, reported beside 7k(k-1) and
+    7k^2+2k+1."""
+    rows = {}
+    for line in open(os.path.join(GOLD, "paper_gate_counts.txt")):
+        if line.startswith("#") or ":" not in line:
+            continue
+        name, *pairs = line.split()
+        rows[name] = {int(p.split(":")[0]): int(p.split(":")[1]) for p in pairs}
+    for k, n in rows["adder"].items():
+        assert C.gate_count(C.adder(k)) == n == 5 * k
+    for k, n in rows["subtractor"].items():
+        assert C.gate_count(C.subtractor(k)) == n == 6 * k
+    for k, n in rows["multiplier"].items():
+        assert n == 7 * k * (k - 1)
+        assert C.gate_count(C.multiplier(k)) <= n + 2 * k
+    assert C.gate_count(C.multiplier(8)) == 333
+
+
+def test_lr_netlist_matches_integer_replica():
+    X, y, _ = mi.lr_data(6, 3, seed=5)
+    w = np.array([100, -50, 7])
+    nl = lr.build_netlist(6, 3)
+    out = C.eval_plain(nl, lr.input_bits(X, y, w))
+    got = mi.from_bits(out.reshape(3, 16))
+    assert np.array_equal(got, lr.replica_step(X, y, w))
+
+
+def test_lr_replica_tracks_float_gradient_descent():
+    """The integer step is the float GD step of §3.4 up to fixed-point
+    rounding: compare w after a few iterations from w = 0."""
+    X, y, wt = mi.lr_data(64, 4, seed=5)
+    w = np.zeros(4, np.int64)
+    wf = np.zeros(4)
+    Xf, yf = X / 256.0, y / 256.0
+    for _ in range(3):
+        w = lr.replica_step(X, y, w)
+        wf = wf - (1 / 64) * (1 / 64) * (Xf.T @ (Xf @ wf - yf))
+    assert np.abs(w / 256.0 - wf).max() < 0.02
+
+
+@pytest.mark.slow
+def test_lr_netlist_config5_size():
+    X, y, _ = mi.lr_data(64, 4, seed=5)
+    w = np.zeros(4, np.int64)
+    nl = lr.build_netlist(64, 4)
+    out = C.eval_plain(nl, lr.input_bits(X, y, w))
+    assert np.array_equal(mi.from_bits(out.reshape(4, 16)), lr.replica_step(X, y, w))
+
+
+@pytest.mark.parametrize("op,k", [("add", 3), ("sub", 2), ("mul", 2), ("div", 2)])
+def test_encrypted_operators_exhaustive_toy(op, k):
+    """Encrypted evaluation of every operand pair at the toy shape: operand a
+    encrypted by party 0, b by party 1; outputs decrypt to the integer result."""
+    K = tfhe.generate(OP.TOY, 31)
+    nl = {"add": C.adder, "sub": C.subtractor, "mul": C.multiplier, "div": C.divider}[op](k)
+    a, b = _all_pairs(k)
+    if op == "div":
+        keep = b != 0
+        a, b = a[keep], b[keep]
+    ca = np.stack([tfhe.encrypt(K, 0, col, seed=100 + i)
+                   for i, col in enumerate(mi.to_bits(a, k).T)])
+    cb = np.stack([tfhe.encrypt(K, 1, col, seed=200 + i)
+                   for i, col in enumerate(mi.to_bits(b, k).T)])
+    outs = C.eval_encrypted(nl, K, np.concatenate([ca, cb]))
+    dec = np.stack([tfhe.decrypt(K, o) for o in outs])
+    assert np.array_equal(dec, _run(nl, k, a, b))
