@@ -173,13 +173,23 @@ int mk_bootstrap_gate(mk_ctx *ctx, const uint8_t *gate_types_dev,
 
 /* Evaluates `batch` independent instances of a netlist (Algs. 3-6).
  * in_dev: [n_inputs][batch][stride] words, out_dev: [n_outputs][batch]
- * [stride] words.  The netlist is levelled by bootstrapping depth; NOT
- * gates are folded into their consumers; every level runs as one batch of
- * all its gates over all instances.  Errors as mk_bootstrap_gate, plus
- * MK_EINVAL for a malformed netlist. */
+ * [stride] words (device memory).  NOT gates and the constant wires are
+ * folded into the consumers' pre-combination (exact mod 2^32), gates that no
+ * output depends on are skipped, and the remaining gates are levelled by
+ * bootstrapping depth; every level runs as one batch of all its gates over
+ * all instances.  The call returns after the work on `stream` has completed.
+ * Errors as mk_bootstrap_gate, plus MK_EINVAL for a malformed netlist
+ * (undefined or redefined wires, gates out of topological order). */
 int mk_eval_circuit(mk_ctx *ctx, const mk_circuit *c, const uint32_t *in_dev,
                     uint32_t *out_dev, size_t batch, size_t stride, int path,
                     void *stream);
+
+/* Host-side analysis of a netlist as mk_eval_circuit levels it: number of
+ * bootstrapping levels, bootstrapped gates actually evaluated, widest level,
+ * and wire slots needed per instance.  Any output pointer may be NULL.
+ * Errors: MK_EINVAL for a malformed netlist. */
+int mk_circuit_stats(const mk_circuit *c, int32_t *n_levels, int64_t *live_gates,
+                     int32_t *max_width, int32_t *slots);
 
 /* Stage entry points (the same kernels as mk_bootstrap_gate, exposed so that
  * each step can be checked on its own).
@@ -198,12 +208,31 @@ int mk_extract_keyswitch(mk_ctx *ctx, const uint32_t *acc_dev,
 /* Netlist builders (§4.3-§4.5).  Each writes into caller-provided arrays
  * sized by a first call with gates == NULL (which only sets *n_gates and
  * *n_wires).  Input wires: operand a bits (LSB first) then operand b bits;
- * output wires: result bits LSB first.
- *   op: 0 adder (k-bit, 5k gates), 1 subtractor (6k gates),
- *       2 multiplier (k x k -> 2k bits, signed), 3 divider (k-bit signed
- *       truncating quotient then remainder, 2k outputs). */
+ * output wires: result bits LSB first.  Operators:
+ *   MK_OP_ADD   k-bit adder, carry-in 0, 5k gates (Alg. 3)
+ *   MK_OP_SUB   k-bit subtractor: k XORs with 1, adder with carry-in 1, 6k
+ *               gates (Alg. 5)
+ *   MK_OP_MUL   signed k x k -> 2k-bit Baugh-Wooley array (Alg. 4's role)
+ *   MK_OP_DIV   signed k-bit / k-bit truncating division: k quotient bits
+ *               then k remainder bits, results mod 2^k (Alg. 6's role)
+ *   MK_OP_DIV2  the same with a 2k-bit dividend (2k + k inputs)
+ * kbits must be in [1, 64] ([2, 64] for MUL and DIV).  Errors: MK_EINVAL. */
+#define MK_OP_ADD 0
+#define MK_OP_SUB 1
+#define MK_OP_MUL 2
+#define MK_OP_DIV 3
+#define MK_OP_DIV2 4
 int mk_build_operator(int op, int kbits, mk_gate *gates, int32_t *n_gates,
                       int32_t *n_wires, int32_t *inputs, int32_t *outputs);
+
+/* One fixed-point gradient-descent step of linear regression (§4.6) on Q8.8
+ * int16 values: r_i = sum_j mulq(x_ij, w_j) - y_i, g_j = sum_i mulq(x_ij,
+ * r_i), w_j' = w_j - (g_j >> shift), with mulq(a,b) = bits 8..23 of a*b and
+ * sums mod 2^16.  Inputs: x (m*d values row-major), y (m), w (d), 16 bits
+ * each LSB first; outputs: w' (d values).  Sizing as mk_build_operator.
+ * Errors: MK_EINVAL (m*d > 4096, shift > 15). */
+int mk_build_lr_step(int m, int d, int shift, mk_gate *gates, int32_t *n_gates,
+                     int32_t *n_wires, int32_t *inputs, int32_t *outputs);
 
 /* Kernel timing.  With level 1, every pipeline stage is bracketed by HIP
  * events recorded on the caller's stream; level 2 also brackets each kernel

@@ -45,6 +45,9 @@ C1 = Params(k=2, n=64, N=256, bk_ell=2, ks_t=6,
 # Same shape with key noise 2^-26, where gates decrypt correctly.
 C1B = Params(k=2, n=64, N=256, bk_ell=2, ks_t=6,
              bk_noise_log2=26, ks_noise_log2=20, lwe_noise_log2=12)
+# C1B shape with 4 parties.
+C1B4 = Params(k=4, n=64, N=256, bk_ell=2, ks_t=6,
+              bk_noise_log2=26, ks_noise_log2=20, lwe_noise_log2=12)
 # Table 7 shape with 2 parties.
 C2 = Params(k=2, n=560, N=1024, bk_ell=3, ks_t=8,
             bk_noise_log2=30, ks_noise_log2=15, lwe_noise_log2=15)

@@ -65,6 +65,12 @@ _SIGS = {
     "mk_build_operator": ([_i, _i, ctypes.POINTER(MkGate), ctypes.POINTER(ctypes.c_int32),
                            ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                            ctypes.POINTER(ctypes.c_int32)], _i),
+    "mk_build_lr_step": ([_i, _i, _i, ctypes.POINTER(MkGate), ctypes.POINTER(ctypes.c_int32),
+                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                          ctypes.POINTER(ctypes.c_int32)], _i),
+    "mk_circuit_stats": ([ctypes.POINTER(MkCircuit), ctypes.POINTER(ctypes.c_int32),
+                          ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
+                          ctypes.POINTER(ctypes.c_int32)], _i),
     "mk_set_profiling": ([_vp, _i], _i),
     "mk_get_profile": ([_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), _i], _i),
     "mk_last_error": ([], ctypes.c_char_p),
@@ -245,20 +251,36 @@ class Circuit:
                          len(g), g.ctypes.data_as(ctypes.POINTER(MkGate)))
 
 
-OP_ADD, OP_SUB, OP_MUL, OP_DIV = 0, 1, 2, 3
+OP_ADD, OP_SUB, OP_MUL, OP_DIV, OP_DIV2 = 0, 1, 2, 3, 4
 
 
-def build_operator(op: int, kbits: int) -> Circuit:
-    """Netlist of a k-bit operator from the library's builders."""
+def _netlist(call, n_in, n_out) -> "Circuit":
     ng, nw = ctypes.c_int32(0), ctypes.c_int32(0)
-    _check(_L.mk_build_operator(op, kbits, None, ctypes.byref(ng), ctypes.byref(nw), None, None))
+    P32 = ctypes.POINTER(ctypes.c_int32)
+    _check(call(None, ctypes.byref(ng), ctypes.byref(nw), None, None))
     gates = np.zeros((ng.value, 4), np.int32)
-    n_in = 2 * kbits
-    n_out = {OP_ADD: kbits, OP_SUB: kbits, OP_MUL: 2 * kbits, OP_DIV: 2 * kbits}[op]
     inputs = np.zeros(n_in, np.int32)
     outputs = np.zeros(n_out, np.int32)
-    P32 = ctypes.POINTER(ctypes.c_int32)
-    _check(_L.mk_build_operator(op, kbits, gates.ctypes.data_as(ctypes.POINTER(MkGate)),
-                                ctypes.byref(ng), ctypes.byref(nw),
-                                inputs.ctypes.data_as(P32), outputs.ctypes.data_as(P32)))
+    _check(call(gates.ctypes.data_as(ctypes.POINTER(MkGate)), ctypes.byref(ng), ctypes.byref(nw),
+                inputs.ctypes.data_as(P32), outputs.ctypes.data_as(P32)))
     return Circuit(nw.value, inputs, outputs, gates)
+
+
+def build_operator(op: int, kbits: int) -> "Circuit":
+    """Netlist of a k-bit operator from the library's builders."""
+    n_in = {OP_DIV2: 3 * kbits}.get(op, 2 * kbits)
+    n_out = {OP_ADD: kbits, OP_SUB: kbits}.get(op, 2 * kbits)
+    return _netlist(lambda *a: _L.mk_build_operator(op, kbits, *a), n_in, n_out)
+
+
+def build_lr_step(m: int, d: int, shift: int = 12) -> "Circuit":
+    """Netlist of one fixed-point gradient-descent step (16-bit values)."""
+    return _netlist(lambda *a: _L.mk_build_lr_step(m, d, shift, *a), 16 * (m * d + m + d), 16 * d)
+
+
+def circuit_stats(c: "Circuit"):
+    """(levels, bootstrapped gates evaluated, widest level, slots per instance)."""
+    nl, ng, mw, sl = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+    _check(_L.mk_circuit_stats(ctypes.byref(c.c()), ctypes.byref(nl), ctypes.byref(ng),
+                               ctypes.byref(mw), ctypes.byref(sl)))
+    return nl.value, ng.value, mw.value, sl.value

@@ -98,7 +98,8 @@ static int check_uploaded(const mk_ctx *ctx) {
 void device_release(mk_ctx *ctx) {
     drain_events(ctx);
     DeviceKeys &D = ctx->dev;
-    void *ptrs[] = {D.bk_ext, D.evk_ext, D.bk_win, D.evk_win, D.ks, D.scratch, D.mfma_scratch};
+    void *ptrs[] = {D.bk_ext, D.evk_ext, D.bk_win, D.evk_win, D.ks, D.scratch, D.mfma_scratch,
+                    D.circ_scratch};
     bool any = false;
     for (void *p : ptrs) any |= p != nullptr;
     if (any) {
@@ -441,7 +442,7 @@ __global__ __launch_bounds__(kKsThreads) void extract_ks_kernel(KsArgs a) {
     if (tid == 0) out[0] = A[0] + 0x20000000u + bsum;
 }
 
-static int launch_extract_ks(mk_ctx *ctx, const uint32_t *acc, uint32_t *out, size_t count,
+int launch_extract_ks(mk_ctx *ctx, const uint32_t *acc, uint32_t *out, size_t count,
                              size_t stride, hipStream_t s) {
     const mk_params &P = ctx->p;
     KsArgs a;

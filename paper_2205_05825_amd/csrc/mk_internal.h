@@ -48,6 +48,8 @@ struct DeviceKeys {
     size_t scratch_bytes = 0;
     void *mfma_scratch = nullptr;
     size_t mfma_scratch_bytes = 0;
+    void *circ_scratch = nullptr;   // circuit wire buffer and descriptors
+    size_t circ_scratch_bytes = 0;
 };
 
 }  // namespace mk

@@ -16,7 +16,7 @@ from oracle import tfhe
 
 FIELDS = ("k", "n", "N", "bk_ell", "ks_t", "bk_noise_log2", "ks_noise_log2",
           "lwe_noise_log2", "bk_log_base", "ks_log_base")
-SEEDS = {"C1": 0, "C1B": 5, "C2": 2, "C3": 3, "TOY": 9}
+SEEDS = {"C1": 0, "C1B": 5, "C1B4": 6, "C2": 2, "C3": 3, "TOY": 9}
 HEADER_BYTES = 4 + 4 + 40 + 4
 
 
@@ -97,3 +97,23 @@ def gpu_world(name):
         ctx.upload()
         ctx._uploaded = True
     return oracle_keys(name), ctx
+
+
+def oracle_circuit(name, nl, in_ct, workers=8):
+    """Oracle gate-by-gate evaluation of netlist nl on in_ct[n_in, B, words],
+    one instance per thread."""
+    from concurrent.futures import ThreadPoolExecutor
+    from oracle import circuits as C
+    K = oracle_keys(name)
+    W = K.params.lwe_words
+    Bn = in_ct.shape[1]
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        outs = list(ex.map(lambda b: C.eval_encrypted(nl, K, in_ct[:, b:b + 1, :W]), range(Bn)))
+    return np.concatenate(outs, axis=1)
+
+
+def encrypt_operands(K, values, bits, party, seed):
+    """u32[bits, B, words]: bit i of every value, encrypted by `party`."""
+    import mk_inputs as mi
+    cols = mi.to_bits(values, bits).T
+    return np.stack([tfhe.encrypt(K, party, col, seed=seed + 1000 * i) for i, col in enumerate(cols)])

@@ -1,0 +1,110 @@
+"""GPU evaluation of the operator netlists through mk_eval_circuit: parity
+with the oracle's gate-by-gate evaluation, and full-size workloads checked by
+decryption against integer arithmetic (needs an MI355X)."""
+import numpy as np
+import pytest
+
+import mk_inputs as mi
+from oracle import circuits as C
+from oracle import lr
+from oracle import tfhe
+from tests import helpers
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+def _eval(torch, ctx, circ, in_ct, path):
+    d = torch.device("cuda:0")
+    inp = torch.from_numpy(np.ascontiguousarray(in_ct).view(np.int32)).to(d)
+    out = torch.full((len(circ.outputs), in_ct.shape[1], in_ct.shape[2]), -1,
+                     dtype=torch.int32, device=d)
+    ctx.eval_circuit(circ, inp, out, path=path)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().view(np.uint32)
+
+
+def _trunc_div(a, b):
+    q = np.abs(a) // np.abs(b) * np.sign(a) * np.sign(b)
+    return q, a - q * b
+
+
+def _wrap(v, k):
+    v = np.asarray(v, np.int64) & ((1 << k) - 1)
+    return np.where(v >= 1 << (k - 1), v - (1 << k), v)
+
+
+OPS = {"add": (0, C.adder), "sub": (1, C.subtractor), "mul": (2, C.multiplier),
+       "div": (3, C.divider)}
+
+
+@pytest.mark.parametrize("path", [0, 1])
+@pytest.mark.parametrize("op", ["add", "sub", "mul", "div"])
+def test_operator_parity_c1b(torch_cuda, op, path):
+    """4-bit operators on 3 operand pairs (a from party 0, b from party 1):
+    every output word equals the oracle's, outputs decrypt correctly."""
+    import paper_2205_05825_amd as mk
+    K, ctx = helpers.gpu_world("C1B")
+    code, build = OPS[op]
+    k = 4
+    circ = mk.build_operator(code, k)
+    a, b = np.array([5, -8, 7]), np.array([-3, 3, -1])
+    in_ct = np.concatenate([helpers.encrypt_operands(K, a, k, 0, 11),
+                            helpers.encrypt_operands(K, b, k, 1, 12)])
+    got = _eval(torch_cuda, ctx, circ, in_ct, path)
+    ref = helpers.oracle_circuit("C1B", build(k), in_ct)
+    assert np.array_equal(got, ref)
+    dec = np.stack([tfhe.decrypt(K, o) for o in got])
+    want = C.eval_plain(build(k), np.concatenate([mi.to_bits(a, k).T, mi.to_bits(b, k).T]))
+    assert np.array_equal(dec, want)
+
+
+def test_paths_agree_on_a_circuit(torch_cuda):
+    import paper_2205_05825_amd as mk
+    K, ctx = helpers.gpu_world("C1B")
+    circ = mk.build_operator(mk.OP_MUL, 6)
+    a, b = mi.operand_pairs(40, 6, seed=3)
+    in_ct = np.concatenate([helpers.encrypt_operands(K, a, 6, 0, 21),
+                            helpers.encrypt_operands(K, b, 6, 1, 22)])
+    x = _eval(torch_cuda, ctx, circ, in_ct, 0)
+    y = _eval(torch_cuda, ctx, circ, in_ct, 1)
+    assert np.array_equal(x, y)
+    dec = mi.from_bits(np.stack([tfhe.decrypt(K, o) for o in y]).T)
+    assert np.array_equal(dec, a * b)
+
+
+def test_four_party_circuit_parity(torch_cuda):
+    """k = 4 parties at a small shape: operand bits spread over all parties."""
+    import paper_2205_05825_amd as mk
+    K, ctx = helpers.gpu_world("C1B4")
+    circ = mk.build_operator(mk.OP_ADD, 3)
+    a, b = np.array([3, -4]), np.array([-2, 1])
+    in_ct = np.concatenate([helpers.encrypt_operands(K, a, 3, 0, 31),
+                            helpers.encrypt_operands(K, b, 3, 3, 32)])
+    got = _eval(torch_cuda, ctx, circ, in_ct, 1)
+    ref = helpers.oracle_circuit("C1B4", C.adder(3), in_ct)
+    assert np.array_equal(got, ref)
+    dec = mi.from_bits(np.stack([tfhe.decrypt(K, o) for o in got]).T)
+    assert np.array_equal(dec, _wrap(a + b, 3))
+
+
+def test_lr_step_small(torch_cuda):
+    """One encrypted gradient-descent step (m=2, d=2) against the replica."""
+    import paper_2205_05825_amd as mk
+    K, ctx = helpers.gpu_world("C1B")
+    X, y, _ = mi.lr_data(2, 2, seed=7)
+    w = np.array([40, -25])
+    circ = mk.build_lr_step(2, 2)
+    bits = lr.input_bits(X, y, w)[:, 0]
+    owner = lr.input_owner(2, 2)
+    in_ct = np.stack([tfhe.encrypt(K, int(owner[i]), [bits[i]], seed=500 + i)
+                      for i in range(len(bits))])
+    got = _eval(torch_cuda, ctx, circ, in_ct, 1)
+    dec = np.stack([tfhe.decrypt(K, o) for o in got])[:, 0]
+    assert np.array_equal(mi.from_bits(dec.reshape(2, 16)), lr.replica_step(X, y, w))

@@ -1,0 +1,109 @@
+"""Full-size workloads on the GPU (needs an MI355X).  Ciphertexts come from
+the library's own encryption; every output is decrypted and compared with
+integer arithmetic.  Bit parity with the oracle at these shapes is covered
+per gate (the oracle is too slow for whole circuits here); whole-circuit
+parity runs at small shapes in test_gpu_circuits.py."""
+import time
+
+import numpy as np
+import pytest
+
+import mk_inputs as mi
+from oracle import params as OP
+from oracle import tfhe
+from tests import helpers
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+def _enc_operand(ctx, values, bits, party, seed):
+    cols = mi.to_bits(values, bits).T
+    return np.stack([ctx.encrypt(party, col, seed=seed + 1000 * i) for i, col in enumerate(cols)])
+
+
+def _run(torch, ctx, circ, in_ct, path=1):
+    d = torch.device("cuda:0")
+    inp = torch.from_numpy(np.ascontiguousarray(in_ct).view(np.int32)).to(d)
+    out = torch.zeros((len(circ.outputs), in_ct.shape[1], in_ct.shape[2]), dtype=torch.int32, device=d)
+    t0 = time.perf_counter()
+    ctx.eval_circuit(circ, inp, out, path=path)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    o = out.cpu().numpy().view(np.uint32)
+    return np.stack([ctx.decrypt(x) for x in o]), dt
+
+
+def _wrap(v, k):
+    v = np.asarray(v, np.int64) & ((1 << k) - 1)
+    return np.where(v >= 1 << (k - 1), v - (1 << k), v)
+
+
+def test_c3_gate_parity_four_parties(torch_cuda):
+    """Single gates at the 4-party Table 7 shape, word for word."""
+    K, ctx = helpers.gpu_world("C3")
+    types, m1, m2 = mi.gate_batch(40, seed=33)
+    c1 = tfhe.encrypt(K, 0, m1, seed=300)
+    c2 = tfhe.encrypt(K, 3, m2, seed=301)
+    d = torch_cuda.device("cuda:0")
+    t = torch_cuda.from_numpy(types).to(d)
+    a = torch_cuda.from_numpy(c1.view(np.int32)).to(d)
+    b = torch_cuda.from_numpy(c2.view(np.int32)).to(d)
+    out = torch_cuda.zeros_like(a)
+    ctx.bootstrap_gate(t, a, b, out, path=1)
+    torch_cuda.cuda.synchronize()
+    got = out.cpu().numpy().view(np.uint32)
+    want = [mi.plain_gate(int(x), int(y), int(z)) for x, y, z in zip(types, m1, m2)]
+    assert tfhe.decrypt(K, got).tolist() == want
+    idx = [0, 17, 39]
+    assert np.array_equal(got[idx], helpers.oracle_gates("C3", types, c1, c2, idx))
+
+
+def test_c3_multiplier_256_pairs(torch_cuda):
+    """8-bit signed multiplier, 256 pairs in [-128, 127], 4 parties; a from
+    party 0, b from party 1; one batch per bootstrapping level."""
+    import paper_2205_05825_amd as mk
+    ctx = helpers.lib_context("C3")
+    if not getattr(ctx, "_uploaded", False):
+        ctx.upload()
+        ctx._uploaded = True
+    circ = mk.build_operator(mk.OP_MUL, 8)
+    a, b = mi.operand_pairs(256, 8, seed=3)
+    in_ct = np.concatenate([_enc_operand(ctx, a, 8, 0, 1), _enc_operand(ctx, b, 8, 1, 2)])
+    dec, dt = _run(torch_cuda, ctx, circ, in_ct)
+    levels, live, width, _ = mk.circuit_stats(circ)
+    print("C3 8-bit multiplier: %d pairs, %d levels, %d gates/pair, %.2f s, %.0f gates/s"
+          % (256, levels, live, dt, live * 256 / dt))
+    assert np.array_equal(mi.from_bits(dec.T), a * b)
+
+
+@pytest.mark.parametrize("op", ["add", "sub", "mul", "div"])
+def test_c4_operators_subset(torch_cuda, op):
+    """16-bit operators at the 2-party shape on 32 pairs each (a sample of
+    the 4096-pair workload), divisors non-zero."""
+    import paper_2205_05825_amd as mk
+    K, ctx = helpers.gpu_world("C2")
+    code = {"add": mk.OP_ADD, "sub": mk.OP_SUB, "mul": mk.OP_MUL, "div": mk.OP_DIV}[op]
+    circ = mk.build_operator(code, 16)
+    a, b = mi.operand_pairs(32, 16, seed=4, nonzero_second=True)
+    in_ct = np.concatenate([_enc_operand(ctx, a, 16, 0, 5), _enc_operand(ctx, b, 16, 1, 6)])
+    dec, dt = _run(torch_cuda, ctx, circ, in_ct)
+    _, live, _, _ = mk.circuit_stats(circ)
+    print("C4 16-bit %s: 32 pairs, %d gates/pair, %.2f s, %.0f gates/s" % (op, live, dt, live * 32 / dt))
+    v = mi.from_bits(dec.T)
+    if op == "add":
+        assert np.array_equal(v, _wrap(a + b, 16))
+    elif op == "sub":
+        assert np.array_equal(v, _wrap(a - b, 16))
+    elif op == "mul":
+        assert np.array_equal(v, a * b)
+    else:
+        q = np.abs(a) // np.abs(b) * np.sign(a) * np.sign(b)
+        assert np.array_equal(mi.from_bits(dec[:16].T), _wrap(q, 16))
+        assert np.array_equal(mi.from_bits(dec[16:].T), _wrap(a - q * b, 16))

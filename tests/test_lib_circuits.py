@@ -1,0 +1,57 @@
+"""The library's netlist builders against the oracle's (identical gate
+lists), and the engine's host-side analysis (CPU only, no GPU calls)."""
+import numpy as np
+import pytest
+
+from oracle import circuits as C
+from oracle import lr
+
+
+def _same(lib, ora):
+    assert lib.n_wires == ora.n_wires
+    assert lib.inputs.tolist() == ora.inputs
+    assert lib.outputs.tolist() == ora.outputs
+    assert lib.gates.tolist() == ora.gates
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 8, 16])
+def test_operator_netlists_match_oracle(k):
+    import paper_2205_05825_amd as mk
+    _same(mk.build_operator(mk.OP_ADD, k), C.adder(k))
+    _same(mk.build_operator(mk.OP_SUB, k), C.subtractor(k))
+    if k >= 2:
+        _same(mk.build_operator(mk.OP_MUL, k), C.multiplier(k))
+        _same(mk.build_operator(mk.OP_DIV, k), C.divider(k))
+        _same(mk.build_operator(mk.OP_DIV2, k), C.divider(k, 2 * k))
+
+
+@pytest.mark.parametrize("m,d", [(1, 1), (3, 2), (64, 4)])
+def test_lr_netlist_matches_oracle(m, d):
+    import paper_2205_05825_amd as mk
+    _same(mk.build_lr_step(m, d), lr.build_netlist(m, d))
+
+
+def test_circuit_stats():
+    import paper_2205_05825_amd as mk
+    add = mk.build_operator(mk.OP_ADD, 8)
+    levels, live, width, slots = mk.circuit_stats(add)
+    # the final carry of the adder is dead: 4 gates dropped
+    assert live == 5 * 8 - 3
+    assert levels >= 8 and width >= 1 and slots >= 16
+    mul = mk.build_operator(mk.OP_MUL, 8)
+    levels, live, width, slots = mk.circuit_stats(mul)
+    assert live == C.gate_count(C.multiplier(8))
+    # slot reuse keeps the wire buffer well below one slot per gate
+    assert slots < 16 + live
+
+
+def test_engine_rejects_malformed_netlists():
+    import paper_2205_05825_amd as mk
+    good = mk.build_operator(mk.OP_ADD, 2)
+    bad = mk.Circuit(good.n_wires, good.inputs, good.outputs, good.gates[::-1].copy())
+    with pytest.raises(mk.MkError) as e:
+        mk.circuit_stats(bad)
+    assert e.value.code == -1
+    dup = mk.Circuit(good.n_wires, np.array([2, 2, 3, 4]), good.outputs, good.gates)
+    with pytest.raises(mk.MkError):
+        mk.circuit_stats(dup)
