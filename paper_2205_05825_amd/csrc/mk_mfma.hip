@@ -248,25 +248,34 @@ __global__ __launch_bounds__(256) void mfma_wdec_kernel(MfmaArgs a, int live) {
 // the previous tile of the row tile above it and only row tile 0 needs a new
 // one: a register window of MR tiles per limb, one new tile per limb per
 // K-block.  Loads run two K-blocks ahead of the MFMAs (a two-slot ring,
-// unrolled so that every register index is static).
+// unrolled so that every register index is static).  They are buffer loads:
+// the descriptors bound every access to the operand blocks (out-of-range
+// reads return 0), and, unlike plain loads, the compiler does not merge the
+// ring's loop-carried loads back into a load at the point of use.
+constexpr uint32_t kBufWord3 = 0x00020000u;  // raw dword buffer, gfx9 family
+
 template <int MR>
-__device__ __forceinline__ void toeplitz_gemm(const int8_t *__restrict__ A,  // [4][ND][1024]
-                                              const int8_t *__restrict__ B,  // [NB][1024]
+__device__ __forceinline__ void toeplitz_gemm(const int8_t *A,  // [4][ND][1024]
+                                              const int8_t *B,  // [NB][1024]
                                               int NB, int mb0, int lane, v16i (&acc)[MR][4]) {
     const int ND = 2 * NB - 1;
-    const int8_t *Al = A + lane * 16;
-    const int8_t *Bl = B + lane * 16;
+    const __amdgpu_buffer_rsrc_t ra =
+        __builtin_amdgcn_make_buffer_rsrc((void *)A, (short)0, 4 * ND * kTileBytes, kBufWord3);
+    const __amdgpu_buffer_rsrc_t rb =
+        __builtin_amdgcn_make_buffer_rsrc((void *)B, (short)0, NB * kTileBytes, kBufWord3);
     auto ldA = [&](int t, int kb) {
-        return *reinterpret_cast<const v4i *>(Al + ((size_t)t * ND + mb0 - kb + NB - 1) * kTileBytes);
+        return (v4i)__builtin_amdgcn_raw_buffer_load_b128(
+            ra, (t * ND + mb0 - kb + NB - 1) * kTileBytes + lane * 16, 0, 0);
     };
-    auto ldB = [&](int kb) { return *reinterpret_cast<const v4i *>(Bl + (size_t)kb * kTileBytes); };
+    auto ldB = [&](int kb) {
+        return (v4i)__builtin_amdgcn_raw_buffer_load_b128(rb, kb * kTileBytes + lane * 16, 0, 0);
+    };
     v4i win[MR][4];
 #pragma unroll
     for (int r = 0; r < MR; ++r)
 #pragma unroll
         for (int t = 0; t < 4; ++t)
-            win[r][t] = *reinterpret_cast<const v4i *>(
-                Al + ((size_t)t * ND + mb0 + r + NB - 1) * kTileBytes);
+            win[r][t] = ldA(t, -r);
     v4i b = ldB(0);
     // ring slot s holds the new tiles of K-block kb+1 (s = kb & 1)
     v4i pa0[4], pa1[4], pb0, pb1;
@@ -357,23 +366,37 @@ __global__ __launch_bounds__(256, 2) void mfma_gemm1_kernel(MfmaArgs a, int part
         toeplitz_gemm<kMR>(A, B, NB, tk.rb * kMR, lane, acc);
     }
     const int g = tk.gt * 32 + (lane & 31);
-    uint32_t *dst = kind == 0 ? a.acc + ((size_t)g * K1 + j) * N
-                              : a.W + ((size_t)j * a.GP + g) * N;
+    // registers 4q..4q+3 of row tile r hold rows m..m+3 of column g
+    if (kind == 0) {
+        uint32_t *dst = a.acc + ((size_t)g * K1 + j) * N;
+        uint4 old[kMR][4];
 #pragma unroll
-    for (int r = 0; r < kMR; ++r)
+        for (int r = 0; r < kMR; ++r)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            // registers 4q..4q+3 hold 4 consecutive rows of one column
-            const int m = 32 * (tk.rb * kMR + r) + 8 * q + 4 * (lane / 32);
-            uint4 *p = reinterpret_cast<uint4 *>(dst + m);
-            uint4 v = make_uint4(combine<kMR>(acc, r, 4 * q + 0), combine<kMR>(acc, r, 4 * q + 1),
-                                 combine<kMR>(acc, r, 4 * q + 2), combine<kMR>(acc, r, 4 * q + 3));
-            if (kind == 0) {
-                const uint4 o = *p;
-                v.x += o.x; v.y += o.y; v.z += o.z; v.w += o.w;
+            for (int q = 0; q < 4; ++q)
+                old[r][q] = *reinterpret_cast<const uint4 *>(
+                    dst + 32 * (tk.rb * kMR + r) + 8 * q + 4 * (lane / 32));
+#pragma unroll
+        for (int r = 0; r < kMR; ++r)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                uint4 v = old[r][q];
+                v.x += combine<kMR>(acc, r, 4 * q + 0);
+                v.y += combine<kMR>(acc, r, 4 * q + 1);
+                v.z += combine<kMR>(acc, r, 4 * q + 2);
+                v.w += combine<kMR>(acc, r, 4 * q + 3);
+                *reinterpret_cast<uint4 *>(dst + 32 * (tk.rb * kMR + r) + 8 * q + 4 * (lane / 32)) = v;
             }
-            *p = v;
-        }
+    } else {
+        uint32_t *dst = a.W + ((size_t)j * a.GP + g) * N;
+#pragma unroll
+        for (int r = 0; r < kMR; ++r)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                *reinterpret_cast<uint4 *>(dst + 32 * (tk.rb * kMR + r) + 8 * q + 4 * (lane / 32)) =
+                    make_uint4(combine<kMR>(acc, r, 4 * q + 0), combine<kMR>(acc, r, 4 * q + 1),
+                               combine<kMR>(acc, r, 4 * q + 2), combine<kMR>(acc, r, 4 * q + 3));
+    }
 }
 
 // Stage 2.  Unit o: ACC_{o ? 1+party : 0} += sum_l T(f_o,l) V_l.
@@ -397,18 +420,22 @@ __global__ __launch_bounds__(256, 2) void mfma_gemm2_kernel(MfmaArgs a, int part
     }
     const int g = tk.gt * 32 + (lane & 31);
     uint32_t *dst = a.acc + ((size_t)g * K1 + (o == 0 ? 0 : 1 + party)) * N;
+    uint4 old[kMR][4];
+#pragma unroll
+    for (int r = 0; r < kMR; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            old[r][q] = *reinterpret_cast<const uint4 *>(dst + 32 * (tk.rb * kMR + r) + 8 * q + 4 * (lane / 32));
 #pragma unroll
     for (int r = 0; r < kMR; ++r)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int m = 32 * (tk.rb * kMR + r) + 8 * q + 4 * (lane / 32);
-            uint4 *p = reinterpret_cast<uint4 *>(dst + m);
-            uint4 v = *p;
+            uint4 v = old[r][q];
             v.x += combine<kMR>(acc, r, 4 * q + 0);
             v.y += combine<kMR>(acc, r, 4 * q + 1);
             v.z += combine<kMR>(acc, r, 4 * q + 2);
             v.w += combine<kMR>(acc, r, 4 * q + 3);
-            *p = v;
+            *reinterpret_cast<uint4 *>(dst + 32 * (tk.rb * kMR + r) + 8 * q + 4 * (lane / 32)) = v;
         }
 }
 
