@@ -39,6 +39,28 @@ PEAK_INT8_OPS = 5.0e15          # MI355X dense int8 MFMA
 PEAK_VALU_TORUS_MACS = 256 * 64 * 2.4e9 / 2
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "mfma_gemm1_c2_1024gates_hbm_traffic.md")
+MFMA_SOURCE = os.path.join(ROOT, "paper_2205_05825_amd", "csrc", "mk_mfma.hip")
+
+
+def measured_traffic():
+    """HBM bytes per stage-1 GEMM launch from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE summary, or None when the kernel source changed
+    since those counters were taken."""
+    import hashlib
+    import re
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        src = hashlib.sha256(open(MFMA_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m = re.search(r"HBM bytes per launch: (\d+)", text)
+    h = re.search(r"sha256 ([0-9a-f]{64})", text)
+    if not m or not h or h.group(1) != src:
+        return None
+    return int(m.group(1))
+
+
 def macs_per_gate(p):
     """Exact Torus32 multiply-adds of one blind rotation: k*n CMux steps, each
     (2k+4)*ell negacyclic products of N^2 multiply-adds."""
@@ -91,7 +113,20 @@ def main():
     ap.add_argument("--path", choices=["mfma", "i32"], default="mfma")
     ap.add_argument("--cpu-gates-per-core", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run one device-to-device copy of MIB MiB (reference "
+                         "kernel for scaling HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.int32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4}))
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on exactly one GPU (the path is per-GPU; "
               "--gpus %d is not supported)" % args.gpus, file=sys.stderr)
@@ -171,7 +206,9 @@ def main():
         g1_ms = ms[4] / max(ln[4], 1)
         achieved = g1_ops / (g1_ms * 1e-3)
         roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_INT8_OPS / 1e12,
-                "unit": "TOP/s", "frac": achieved / PEAK_INT8_OPS, "traffic": None,
+                "unit": "TOP/s", "frac": achieved / PEAK_INT8_OPS, "traffic": measured_traffic(),
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                "copy-calibrated)",
                 "kernel": "mfma_gemm1_kernel", "avg_launch_ms": g1_ms,
                 "launches": ln[4],
                 "whole_rotation_tops": 8 * macs / (br_ms * 1e-3) / 1e12}
