@@ -157,6 +157,8 @@ def main():
 
     paths = {"mfma": mk.PATH_MFMA_I8, "i32": mk.PATH_I32}
     head = paths[args.path]
+    # the autotuner times every GEMM tile shape for this batch size
+    tiles = ctx.autotune(BATCH)
     # correctness gate before timing: outputs decrypt and both paths agree
     outs = {}
     for name, path in paths.items():
@@ -226,6 +228,7 @@ def main():
         "config": {"workload": "1024 mixed bootstrapped MK gates (AND/OR/NOR/XOR/XNOR/NAND), "
                                "k=2 n=560 N=1024 B=2^8 ell=3 B'=2^2 t=8",
                    "global_batch": BATCH, "path": args.path, "parallelism": "single GPU"},
+        "tiles": {"gemm1_shape": tiles[0], "gemm2_shape": tiles[1], "candidate_ms": tiles[2]},
         "stage_ms_per_step": {"precombine": ms[0], "blind_rotate": ms[1],
                               "extract_keyswitch": ms[2], "mfma_gemm1": ms[4], "mfma_gemm2": ms[5],
                               "rotdec": ms[6], "wdec": ms[7]},

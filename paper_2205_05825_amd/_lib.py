@@ -71,6 +71,10 @@ _SIGS = {
     "mk_circuit_stats": ([ctypes.POINTER(MkCircuit), ctypes.POINTER(ctypes.c_int32),
                           ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
                           ctypes.POINTER(ctypes.c_int32)], _i),
+    "mk_autotune": ([_vp, _sz, _vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                     ctypes.POINTER(ctypes.c_float)], _i),
+    "mk_set_tiles": ([_vp, _i, _i], _i),
+    "mk_get_tiles": ([_vp, _sz, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], _i),
     "mk_set_profiling": ([_vp, _i], _i),
     "mk_get_profile": ([_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), _i], _i),
     "mk_last_error": ([], ctypes.c_char_p),
@@ -194,6 +198,23 @@ class Context:
         out = np.zeros((b.shape[0], stride), np.uint32)
         _check(_L.mk_trivial(self._h, bp, b.shape[0], out.ctypes.data_as(ctypes.c_void_p), stride))
         return out
+
+    # ---- tile shapes of the MFMA rotation ----
+    def autotune(self, count: int, stream=None):
+        """Times every GEMM tile shape for batches of `count` gates, keeps the
+        fastest; returns (gemm1 shape, gemm2 shape, ms[6])."""
+        v1, v2 = ctypes.c_int32(), ctypes.c_int32()
+        ms = (ctypes.c_float * 6)()
+        _check(_L.mk_autotune(self._h, count, _stream(stream), ctypes.byref(v1), ctypes.byref(v2), ms))
+        return v1.value, v2.value, list(ms)
+
+    def set_tiles(self, gemm1_shape: int = -1, gemm2_shape: int = -1):
+        _check(_L.mk_set_tiles(self._h, gemm1_shape, gemm2_shape))
+
+    def get_tiles(self, count: int):
+        v1, v2 = ctypes.c_int32(), ctypes.c_int32()
+        _check(_L.mk_get_tiles(self._h, count, ctypes.byref(v1), ctypes.byref(v2)))
+        return v1.value, v2.value
 
     # ---- profiling ----
     def set_profiling(self, level: int):

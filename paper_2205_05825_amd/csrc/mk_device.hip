@@ -108,8 +108,13 @@ void device_release(mk_ctx *ctx) {
             if (p) (void)hipFree(p);
     }
     const int prof = D.profiling;
+    const auto tuned = D.tuned_tiles;
+    const int f0 = D.force_tiles[0], f1 = D.force_tiles[1];
     D = DeviceKeys();
     D.profiling = prof;
+    D.tuned_tiles = tuned;
+    D.force_tiles[0] = f0;
+    D.force_tiles[1] = f1;
 }
 
 template <class T>

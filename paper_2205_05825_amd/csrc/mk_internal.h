@@ -4,6 +4,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <map>
 #include <string>
 #include <utility>
 #include <vector>
@@ -50,6 +51,10 @@ struct DeviceKeys {
     size_t mfma_scratch_bytes = 0;
     void *circ_scratch = nullptr;   // circuit wire buffer and descriptors
     size_t circ_scratch_bytes = 0;
+    // GEMM tile shapes of the MFMA rotation: autotuned per batch size (in
+    // 32-gate tiles) and optionally forced (-1 = not forced).
+    std::map<int, std::pair<int, int>> tuned_tiles;
+    int force_tiles[2] = {-1, -1};
 };
 
 }  // namespace mk

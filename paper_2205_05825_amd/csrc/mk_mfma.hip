@@ -254,31 +254,35 @@ __global__ __launch_bounds__(256) void mfma_wdec_kernel(MfmaArgs a, int live) {
 // ring's loop-carried loads back into a load at the point of use.
 constexpr uint32_t kBufWord3 = 0x00020000u;  // raw dword buffer, gfx9 family
 
-template <int MR>
+template <int MR, int NC>
 __device__ __forceinline__ void toeplitz_gemm(const int8_t *A,  // [4][ND][1024]
-                                              const int8_t *B,  // [NB][1024]
-                                              int NB, int mb0, int lane, v16i (&acc)[MR][4]) {
+                                              const int8_t *B,  // NC x [NB][1024], contiguous
+                                              int nc_valid, int NB, int mb0, int lane,
+                                              v16i (&acc)[MR][NC][4]) {
     const int ND = 2 * NB - 1;
     const __amdgpu_buffer_rsrc_t ra =
         __builtin_amdgcn_make_buffer_rsrc((void *)A, (short)0, 4 * ND * kTileBytes, kBufWord3);
+    // gate tiles beyond nc_valid (ragged last group) read as zero
     const __amdgpu_buffer_rsrc_t rb =
-        __builtin_amdgcn_make_buffer_rsrc((void *)B, (short)0, NB * kTileBytes, kBufWord3);
+        __builtin_amdgcn_make_buffer_rsrc((void *)B, (short)0, nc_valid * NB * kTileBytes, kBufWord3);
     auto ldA = [&](int t, int kb) {
         return (v4i)__builtin_amdgcn_raw_buffer_load_b128(
             ra, (t * ND + mb0 - kb + NB - 1) * kTileBytes + lane * 16, 0, 0);
     };
-    auto ldB = [&](int kb) {
-        return (v4i)__builtin_amdgcn_raw_buffer_load_b128(rb, kb * kTileBytes + lane * 16, 0, 0);
+    auto ldB = [&](int c, int kb) {
+        return (v4i)__builtin_amdgcn_raw_buffer_load_b128(
+            rb, (c * NB + kb) * kTileBytes + lane * 16, 0, 0);
     };
     v4i win[MR][4];
 #pragma unroll
     for (int r = 0; r < MR; ++r)
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
-            win[r][t] = ldA(t, -r);
-    v4i b = ldB(0);
-    // ring slot s holds the new tiles of K-block kb+1 (s = kb & 1)
-    v4i pa0[4], pa1[4], pb0, pb1;
+        for (int t = 0; t < 4; ++t) win[r][t] = ldA(t, -r);
+    v4i b[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) b[c] = ldB(c, 0);
+    // ring slot s holds the operands of K-block kb+1 (s = kb & 1)
+    v4i pa0[4], pa1[4], pb0[NC], pb1[NC];
     {
         const int k1 = NB > 1 ? 1 : 0, k2 = NB > 2 ? 2 : NB - 1;
 #pragma unroll
@@ -286,26 +290,34 @@ __device__ __forceinline__ void toeplitz_gemm(const int8_t *A,  // [4][ND][1024]
             pa0[t] = ldA(t, k1);
             pa1[t] = ldA(t, k2);
         }
-        pb0 = ldB(k1);
-        pb1 = ldB(k2);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            pb0[c] = ldB(c, k1);
+            pb1[c] = ldB(c, k2);
+        }
     }
-    auto step = [&](int kb, v4i (&pa)[4], v4i &pb) {
+    auto step = [&](int kb, v4i (&pa)[4], v4i (&pb)[NC]) {
 #pragma unroll
         for (int r = 0; r < MR; ++r)
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
-                acc[r][t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(win[r][t], b, acc[r][t], 0, 0, 0);
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    acc[r][c][t] =
+                        __builtin_amdgcn_mfma_i32_32x32x32_i8(win[r][t], b[c], acc[r][c][t], 0, 0, 0);
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
 #pragma unroll
             for (int r = MR - 1; r > 0; --r) win[r][t] = win[r - 1][t];
             win[0][t] = pa[t];
         }
-        b = pb;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) b[c] = pb[c];
         const int kf = kb + 3 < NB ? kb + 3 : NB - 1;  // clamped: stays in range
 #pragma unroll
         for (int t = 0; t < 4; ++t) pa[t] = ldA(t, kf);
-        pb = ldB(kf);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) pb[c] = ldB(c, kf);
     };
     for (int kb = 0; kb < NB; kb += 2) {  // NB is even (N >= 64)
         step(kb, pa0, pb0);
@@ -313,130 +325,171 @@ __device__ __forceinline__ void toeplitz_gemm(const int8_t *A,  // [4][ND][1024]
     }
 }
 
-// Recombines the limbs of output register e of row tile r.
-template <int MR>
-__device__ __forceinline__ uint32_t combine(const v16i (&acc)[MR][4], int r, int e) {
-    return (uint32_t)acc[r][0][e] + ((uint32_t)acc[r][1][e] << 8) +
-           ((uint32_t)acc[r][2][e] << 16) + ((uint32_t)acc[r][3][e] << 24);
+// Recombines the limbs of output register e of row tile r, gate tile c.
+template <int MR, int NC>
+__device__ __forceinline__ uint32_t combine(const v16i (&acc)[MR][NC][4], int r, int c, int e) {
+    return (uint32_t)acc[r][c][0][e] + ((uint32_t)acc[r][c][1][e] << 8) +
+           ((uint32_t)acc[r][c][2][e] << 16) + ((uint32_t)acc[r][c][3][e] << 24);
 }
 
-constexpr int kMR = 2;      // row tiles (of 32) per wave
-constexpr int kWaves = 4;   // waves per workgroup, one 32-gate tile each
+constexpr int kWaves = 4;   // waves per workgroup
 
-// Task decode shared by both GEMMs: the gate group (kWaves gate tiles) is the
-// fastest index, so with 8 gate groups each XCD keeps one group's digits in
-// its L2, while the key tiles of a (unit, row block) are shared by the four
-// waves of a workgroup through the CU's L1.
+// Task decode shared by both GEMMs.  A wave owns MR row tiles (of 32 rows)
+// of NC consecutive 32-gate tiles; a workgroup's four waves share the row
+// block and the unit (so the key tiles they load are shared through the
+// CU's L1) and cover 4 NC gate tiles.  The gate group is the fastest index:
+// with 8 gate groups each XCD keeps one group's digits in its L2.
 struct Task {
-    int unit, rb, gt;
+    int unit, rb, gt0, nc_valid;
 };
+template <int NC>
 __device__ __forceinline__ Task decode_task(int GT, int RB) {
-    const int GG = (GT + kWaves - 1) / kWaves;
+    const int GG = (GT + kWaves * NC - 1) / (kWaves * NC);
     int task = blockIdx.x;
     Task t;
     const int gg = task % GG;
     task /= GG;
     t.rb = task % RB;
     t.unit = task / RB;
-    t.gt = gg * kWaves + (int)(threadIdx.x / 64);
+    t.gt0 = (gg * kWaves + (int)(threadIdx.x / 64)) * NC;
+    t.nc_valid = GT - t.gt0 < NC ? GT - t.gt0 : NC;
     return t;
+}
+
+// out[rows of the wave's tiles] (+)= limb-combined accumulators, for the
+// valid gate tiles; `rmw` adds to the old contents.  Registers 4q..4q+3 of
+// row tile r hold rows m..m+3 of one column (gate).
+template <int MR, int NC>
+__device__ __forceinline__ void store_tiles(uint32_t *base, size_t gate_stride, const Task &tk,
+                                            int MRrows, int lane, const v16i (&acc)[MR][NC][4],
+                                            bool rmw) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        if (c >= tk.nc_valid) break;
+        const int g = (tk.gt0 + c) * 32 + (lane & 31);
+        uint32_t *dst = base + (size_t)g * gate_stride;
+#pragma unroll
+        for (int r = 0; r < MR; ++r) {
+            uint32_t *row = dst + 32 * (tk.rb * MRrows + r) + 4 * (lane / 32);
+            uint4 old[4];
+            if (rmw) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) old[q] = *reinterpret_cast<const uint4 *>(row + 8 * q);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                uint4 v = make_uint4(combine<MR, NC>(acc, r, c, 4 * q + 0),
+                                     combine<MR, NC>(acc, r, c, 4 * q + 1),
+                                     combine<MR, NC>(acc, r, c, 4 * q + 2),
+                                     combine<MR, NC>(acc, r, c, 4 * q + 3));
+                if (rmw) {
+                    v.x += old[q].x;
+                    v.y += old[q].y;
+                    v.z += old[q].z;
+                    v.w += old[q].w;
+                }
+                *reinterpret_cast<uint4 *>(row + 8 * q) = v;
+            }
+        }
+    }
 }
 
 // Stage 1.  Unit u < live adds c'_u = sum_l T(d_l) U_{u,l} into ACC_u; unit
 // u = live+j writes the partial w_j = sum_l T(b_{j,l}) U_{j,l} to Wp[j].
 // Slots j >= live are identically zero (see launch_br_mfma) and skipped.
-__global__ __launch_bounds__(256, 2) void mfma_gemm1_kernel(MfmaArgs a, int party, int bit, int live) {
+template <int MR, int NC, int OCC>
+__global__ __launch_bounds__(256, OCC) void mfma_gemm1_kernel(MfmaArgs a, int party, int bit, int live) {
     const int N = a.N, NB = N / 32, ND = 2 * NB - 1, K1 = a.k + 1, ell = a.ell;
     const int GT = a.GP / 32;
-    const Task tk = decode_task(GT, NB / kMR);
-    if (tk.gt >= GT) return;
+    const Task tk = decode_task<NC>(GT, NB / MR);
+    if (tk.nc_valid <= 0) return;
     const int lane = threadIdx.x & 63;
     const int kind = tk.unit / live, j = tk.unit % live;
-    v16i acc[kMR][4];
+    v16i acc[MR][NC][4];
 #pragma unroll
-    for (int r = 0; r < kMR; ++r)
+    for (int r = 0; r < MR; ++r)
 #pragma unroll
-        for (int t = 0; t < 4; ++t) acc[r][t] = v16i{};
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc[r][c][t] = v16i{};
     const size_t poly_tiles = (size_t)4 * ND * kTileBytes;
     for (int l = 0; l < ell; ++l) {
         const int8_t *A = kind == 0
             ? a.bk + ((((size_t)party * a.n + bit) * 3 + 0) * ell + l) * poly_tiles
             : a.evk + ((size_t)j * ell + l) * poly_tiles;
-        const int8_t *B = a.U + ((size_t)(j * ell + l) * GT + tk.gt) * NB * kTileBytes;
-        toeplitz_gemm<kMR>(A, B, NB, tk.rb * kMR, lane, acc);
+        const int8_t *B = a.U + ((size_t)(j * ell + l) * GT + tk.gt0) * NB * kTileBytes;
+        toeplitz_gemm<MR, NC>(A, B, tk.nc_valid, NB, tk.rb * MR, lane, acc);
     }
-    const int g = tk.gt * 32 + (lane & 31);
-    // registers 4q..4q+3 of row tile r hold rows m..m+3 of column g
-    if (kind == 0) {
-        uint32_t *dst = a.acc + ((size_t)g * K1 + j) * N;
-        uint4 old[kMR][4];
-#pragma unroll
-        for (int r = 0; r < kMR; ++r)
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                old[r][q] = *reinterpret_cast<const uint4 *>(
-                    dst + 32 * (tk.rb * kMR + r) + 8 * q + 4 * (lane / 32));
-#pragma unroll
-        for (int r = 0; r < kMR; ++r)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                uint4 v = old[r][q];
-                v.x += combine<kMR>(acc, r, 4 * q + 0);
-                v.y += combine<kMR>(acc, r, 4 * q + 1);
-                v.z += combine<kMR>(acc, r, 4 * q + 2);
-                v.w += combine<kMR>(acc, r, 4 * q + 3);
-                *reinterpret_cast<uint4 *>(dst + 32 * (tk.rb * kMR + r) + 8 * q + 4 * (lane / 32)) = v;
-            }
-    } else {
-        uint32_t *dst = a.W + ((size_t)j * a.GP + g) * N;
-#pragma unroll
-        for (int r = 0; r < kMR; ++r)
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                *reinterpret_cast<uint4 *>(dst + 32 * (tk.rb * kMR + r) + 8 * q + 4 * (lane / 32)) =
-                    make_uint4(combine<kMR>(acc, r, 4 * q + 0), combine<kMR>(acc, r, 4 * q + 1),
-                               combine<kMR>(acc, r, 4 * q + 2), combine<kMR>(acc, r, 4 * q + 3));
-    }
+    uint32_t *base = kind == 0 ? a.acc + (size_t)j * N : a.W + (size_t)j * a.GP * N;
+    const size_t gate_stride = kind == 0 ? (size_t)K1 * N : (size_t)N;
+    store_tiles<MR, NC>(base, gate_stride, tk, MR, lane, acc, kind == 0);
 }
 
 // Stage 2.  Unit o: ACC_{o ? 1+party : 0} += sum_l T(f_o,l) V_l.
-__global__ __launch_bounds__(256, 2) void mfma_gemm2_kernel(MfmaArgs a, int party, int bit) {
+template <int MR, int NC, int OCC>
+__global__ __launch_bounds__(256, OCC) void mfma_gemm2_kernel(MfmaArgs a, int party, int bit) {
     const int N = a.N, NB = N / 32, ND = 2 * NB - 1, K1 = a.k + 1, ell = a.ell;
     const int GT = a.GP / 32;
-    const Task tk = decode_task(GT, NB / kMR);
-    if (tk.gt >= GT) return;
+    const Task tk = decode_task<NC>(GT, NB / MR);
+    if (tk.nc_valid <= 0) return;
     const int lane = threadIdx.x & 63;
     const int o = tk.unit;
-    v16i acc[kMR][4];
+    v16i acc[MR][NC][4];
 #pragma unroll
-    for (int r = 0; r < kMR; ++r)
+    for (int r = 0; r < MR; ++r)
 #pragma unroll
-        for (int t = 0; t < 4; ++t) acc[r][t] = v16i{};
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc[r][c][t] = v16i{};
     const size_t poly_tiles = (size_t)4 * ND * kTileBytes;
     for (int l = 0; l < ell; ++l) {
         const int8_t *A = a.bk + ((((size_t)party * a.n + bit) * 3 + 1 + o) * ell + l) * poly_tiles;
-        const int8_t *B = a.V + ((size_t)l * GT + tk.gt) * NB * kTileBytes;
-        toeplitz_gemm<kMR>(A, B, NB, tk.rb * kMR, lane, acc);
+        const int8_t *B = a.V + ((size_t)l * GT + tk.gt0) * NB * kTileBytes;
+        toeplitz_gemm<MR, NC>(A, B, tk.nc_valid, NB, tk.rb * MR, lane, acc);
     }
-    const int g = tk.gt * 32 + (lane & 31);
-    uint32_t *dst = a.acc + ((size_t)g * K1 + (o == 0 ? 0 : 1 + party)) * N;
-    uint4 old[kMR][4];
-#pragma unroll
-    for (int r = 0; r < kMR; ++r)
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            old[r][q] = *reinterpret_cast<const uint4 *>(dst + 32 * (tk.rb * kMR + r) + 8 * q + 4 * (lane / 32));
-#pragma unroll
-    for (int r = 0; r < kMR; ++r)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            uint4 v = old[r][q];
-            v.x += combine<kMR>(acc, r, 4 * q + 0);
-            v.y += combine<kMR>(acc, r, 4 * q + 1);
-            v.z += combine<kMR>(acc, r, 4 * q + 2);
-            v.w += combine<kMR>(acc, r, 4 * q + 3);
-            *reinterpret_cast<uint4 *>(dst + 32 * (tk.rb * kMR + r) + 8 * q + 4 * (lane / 32)) = v;
-        }
+    store_tiles<MR, NC>(a.acc + (size_t)(o == 0 ? 0 : 1 + party) * N, (size_t)K1 * N, tk, MR, lane,
+                        acc, true);
+}
+
+// Tile configurations of the two GEMMs (rows per wave MR x gate tiles per
+// wave NC, waves per SIMD OCC).  The autotuner picks one per batch shape.
+struct GemmShape {
+    int MR, NC;
+};
+constexpr GemmShape kShapes[] = {{2, 1}, {4, 1}, {2, 2}};
+constexpr int kNumShapes = 3;
+
+template <int V>
+struct ShapeOf;
+template <> struct ShapeOf<0> { static constexpr int MR = 2, NC = 1, OCC = 2; };
+template <> struct ShapeOf<1> { static constexpr int MR = 4, NC = 1, OCC = 1; };
+template <> struct ShapeOf<2> { static constexpr int MR = 2, NC = 2, OCC = 1; };
+
+template <int V>
+static void launch_g1(const MfmaArgs &a, int party, int bit, int live, int GT, int NB, hipStream_t s) {
+    using S = ShapeOf<V>;
+    const int GG = (GT + kWaves * S::NC - 1) / (kWaves * S::NC);
+    const unsigned g = (unsigned)(2 * live * (NB / S::MR) * GG);
+    hipLaunchKernelGGL((mfma_gemm1_kernel<S::MR, S::NC, S::OCC>), dim3(g), dim3(64 * kWaves), 0, s, a,
+                       party, bit, live);
+}
+template <int V>
+static void launch_g2(const MfmaArgs &a, int party, int bit, int GT, int NB, hipStream_t s) {
+    using S = ShapeOf<V>;
+    const int GG = (GT + kWaves * S::NC - 1) / (kWaves * S::NC);
+    const unsigned g = (unsigned)(2 * (NB / S::MR) * GG);
+    hipLaunchKernelGGL((mfma_gemm2_kernel<S::MR, S::NC, S::OCC>), dim3(g), dim3(64 * kWaves), 0, s, a,
+                       party, bit);
+}
+static void gemm1(int v, const MfmaArgs &a, int party, int bit, int live, int GT, int NB, hipStream_t s) {
+    if (v == 1) launch_g1<1>(a, party, bit, live, GT, NB, s);
+    else if (v == 2) launch_g1<2>(a, party, bit, live, GT, NB, s);
+    else launch_g1<0>(a, party, bit, live, GT, NB, s);
+}
+static void gemm2(int v, const MfmaArgs &a, int party, int bit, int GT, int NB, hipStream_t s) {
+    if (v == 1) launch_g2<1>(a, party, bit, GT, NB, s);
+    else if (v == 2) launch_g2<2>(a, party, bit, GT, NB, s);
+    else launch_g2<0>(a, party, bit, GT, NB, s);
 }
 
 __global__ void mfma_copyout_kernel(const uint32_t *__restrict__ src, uint32_t *__restrict__ dst,
@@ -447,13 +500,13 @@ __global__ void mfma_copyout_kernel(const uint32_t *__restrict__ src, uint32_t *
 
 static inline unsigned blocks(size_t threads, int per) { return (unsigned)((threads + per - 1) / per); }
 
-int launch_br_mfma(mk_ctx *ctx, const uint32_t *abar, uint32_t *acc_out, size_t count, int steps,
-                   hipStream_t s) {
+// Allocates (grows) the MFMA scratch for `count` gates and fills the kernel
+// arguments.
+static int prepare(mk_ctx *ctx, const uint32_t *abar, size_t count, hipStream_t s, MfmaArgs &a) {
     const mk_params &P = ctx->p;
     if (P.N < kDigCoef) return fail(MK_EPARAM, "int8-MFMA path needs N >= 128");
     const size_t GP = (count + 31) / 32 * 32;
     const int K1 = P.k + 1, N = P.N, ell = P.bk_ell;
-    // a scratch region owned by the MFMA path (grown on demand)
     const size_t acc_b = GP * K1 * N * 4, w_b = (size_t)K1 * GP * N * 4;
     const size_t u_b = (size_t)K1 * ell * GP * N, v_b = (size_t)ell * GP * N;
     DeviceKeys &D = ctx->dev;
@@ -472,7 +525,6 @@ int launch_br_mfma(mk_ctx *ctx, const uint32_t *abar, uint32_t *acc_out, size_t 
         D.mfma_scratch_bytes = need;
     }
     char *sp = (char *)D.mfma_scratch;
-    MfmaArgs a;
     a.k = P.k; a.n = P.n; a.N = N; a.ell = ell; a.log2N = __builtin_ctz(N);
     a.GP = (int)GP; a.G = (int)count;
     a.offset = decomp_offset(ell);
@@ -483,15 +535,40 @@ int launch_br_mfma(mk_ctx *ctx, const uint32_t *abar, uint32_t *acc_out, size_t 
     a.V = (int8_t *)(sp + acc_b + w_b + u_b);
     a.bk = D.bk_win;
     a.evk = D.evk_win;
+    return MK_OK;
+}
+
+// Tile shapes for a batch of GT gate tiles: forced by mk_set_tiles, else the
+// autotuned choice for this size, else shape 0.
+static void shapes_for(const mk_ctx *ctx, int GT, int &v1, int &v2) {
+    const DeviceKeys &D = ctx->dev;
+    v1 = v2 = 0;
+    auto it = D.tuned_tiles.find(GT);
+    if (it != D.tuned_tiles.end()) {
+        v1 = it->second.first;
+        v2 = it->second.second;
+    }
+    if (D.force_tiles[0] >= 0) v1 = D.force_tiles[0];
+    if (D.force_tiles[1] >= 0) v2 = D.force_tiles[1];
+}
+
+int launch_br_mfma(mk_ctx *ctx, const uint32_t *abar, uint32_t *acc_out, size_t count, int steps,
+                   hipStream_t s) {
+    const mk_params &P = ctx->p;
+    MfmaArgs a;
+    int rc = prepare(ctx, abar, count, s, a);
+    if (rc) return rc;
+    const int K1 = P.k + 1, N = P.N;
+    const size_t GP = (size_t)a.GP;
     const int NB = N / 32, GT = (int)(GP / 32);
+    int v1, v2;
+    shapes_for(ctx, GT, v1, v2);
     {
         StageTimer tm(ctx, 1, s);
         hipLaunchKernelGGL(mfma_init_kernel, dim3(blocks(GP * K1 * N, 256)), dim3(256), 0, s, a);
         MK_HIP(hipGetLastError(), "mfma init launch");
         const int KG = NB / kDigKB;
         const unsigned wd_blocks = (unsigned)(GT * KG);
-        const int GG = (GT + kWaves - 1) / kWaves;
-        const unsigned g2 = (unsigned)(2 * (NB / kMR) * GG);
         for (int st = 0; st < steps; ++st) {
             const int party = st / P.n, bit = st % P.n;
             // ACC starts as (X^-b v, 0, .., 0) and during party i's steps only
@@ -500,14 +577,13 @@ int launch_br_mfma(mk_ctx *ctx, const uint32_t *abar, uint32_t *acc_out, size_t 
             // exactly zero: their digits, products and partial sums are skipped.
             const int live = std::min(K1, party + 2);
             const unsigned rd_blocks = (unsigned)(live * GT * KG);
-            const unsigned g1 = (unsigned)(2 * live * (NB / kMR) * GG);
             {
                 StageTimer t6(ctx, 6, s);
                 hipLaunchKernelGGL(mfma_rotdec_kernel, dim3(rd_blocks), dim3(256), 0, s, a, st);
             }
             {
                 StageTimer t4(ctx, 4, s);
-                hipLaunchKernelGGL(mfma_gemm1_kernel, dim3(g1), dim3(64 * kWaves), 0, s, a, party, bit, live);
+                gemm1(v1, a, party, bit, live, GT, NB, s);
             }
             {
                 StageTimer t7(ctx, 7, s);
@@ -515,7 +591,7 @@ int launch_br_mfma(mk_ctx *ctx, const uint32_t *abar, uint32_t *acc_out, size_t 
             }
             {
                 StageTimer t5(ctx, 5, s);
-                hipLaunchKernelGGL(mfma_gemm2_kernel, dim3(g2), dim3(64 * kWaves), 0, s, a, party, bit);
+                gemm2(v2, a, party, bit, GT, NB, s);
             }
         }
         MK_HIP(hipGetLastError(), "mfma step launch");
@@ -526,4 +602,91 @@ int launch_br_mfma(mk_ctx *ctx, const uint32_t *abar, uint32_t *acc_out, size_t 
     return MK_OK;
 }
 
+// Times every tile shape of both GEMMs on the scratch buffers of a batch of
+// `count` gates (contents irrelevant: only durations are read) and records
+// the fastest for this batch size.
+int autotune(mk_ctx *ctx, size_t count, hipStream_t s, int *v1_out, int *v2_out, float *ms_out) {
+    const mk_params &P = ctx->p;
+    MfmaArgs a;
+    int rc = prepare(ctx, nullptr, count, s, a);
+    if (rc) return rc;
+    const int NB = P.N / 32, GT = a.GP / 32;
+    const int party = P.k - 1, live = std::min(P.k + 1, party + 2);
+    hipEvent_t e0, e1;
+    MK_HIP(hipEventCreate(&e0), "autotune event");
+    MK_HIP(hipEventCreate(&e1), "autotune event");
+    constexpr int kReps = 4;
+    float best[2] = {1e30f, 1e30f};
+    int pick[2] = {0, 0};
+    for (int which = 0; which < 2; ++which)
+        for (int v = 0; v < kNumShapes; ++v) {
+            if (NB % kShapes[v].MR) continue;
+            auto run = [&]() {
+                if (which == 0) gemm1(v, a, party, 0, live, GT, NB, s);
+                else gemm2(v, a, party, 0, GT, NB, s);
+            };
+            run();  // warm-up
+            (void)hipEventRecord(e0, s);
+            for (int r = 0; r < kReps; ++r) run();
+            (void)hipEventRecord(e1, s);
+            float ms = 0;
+            if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                return fail(MK_EDEVICE, "autotune timing failed");
+            }
+            if (ms_out) ms_out[which * kNumShapes + v] = ms / kReps;
+            if (ms < best[which]) {
+                best[which] = ms;
+                pick[which] = v;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    MK_HIP(hipGetLastError(), "autotune launch");
+    ctx->dev.tuned_tiles[GT] = {pick[0], pick[1]};
+    if (v1_out) *v1_out = pick[0];
+    if (v2_out) *v2_out = pick[1];
+    return MK_OK;
+}
+
 }  // namespace mk
+
+using namespace mk;
+
+extern "C" {
+
+int mk_autotune(mk_ctx *ctx, size_t count, void *stream, int32_t *gemm1_shape, int32_t *gemm2_shape,
+                float *ms) {
+    if (!ctx || !count) return fail(MK_EINVAL, "mk_autotune: bad argument");
+    if (!ctx->dev.uploaded) return fail(MK_ESTATE, "evaluation key not uploaded (mk_upload_eval_key)");
+    int v1 = 0, v2 = 0;
+    const int rc = autotune(ctx, count, (hipStream_t)stream, &v1, &v2, ms);
+    if (gemm1_shape) *gemm1_shape = v1;
+    if (gemm2_shape) *gemm2_shape = v2;
+    return rc;
+}
+
+int mk_set_tiles(mk_ctx *ctx, int gemm1_shape, int gemm2_shape) {
+    if (!ctx || gemm1_shape < -1 || gemm1_shape >= kNumShapes || gemm2_shape < -1 ||
+        gemm2_shape >= kNumShapes)
+        return fail(MK_EINVAL, "mk_set_tiles: shape out of range");
+    const int NB = ctx->p.N / 32;
+    if ((gemm1_shape >= 0 && NB % kShapes[gemm1_shape].MR) ||
+        (gemm2_shape >= 0 && NB % kShapes[gemm2_shape].MR))
+        return fail(MK_EINVAL, "mk_set_tiles: shape does not divide N/32");
+    ctx->dev.force_tiles[0] = gemm1_shape;
+    ctx->dev.force_tiles[1] = gemm2_shape;
+    return MK_OK;
+}
+
+int mk_get_tiles(const mk_ctx *ctx, size_t count, int32_t *gemm1_shape, int32_t *gemm2_shape) {
+    if (!ctx) return fail(MK_EINVAL, "mk_get_tiles: null context");
+    int v1, v2;
+    shapes_for(ctx, (int)((count + 31) / 32), v1, v2);
+    if (gemm1_shape) *gemm1_shape = v1;
+    if (gemm2_shape) *gemm2_shape = v2;
+    return MK_OK;
+}
+
+}  // extern "C"

@@ -183,3 +183,47 @@ def test_not_gate(torch_cuda):
     ctx.lwe_not(t, out)
     torch_cuda.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy().view(np.uint32), tfhe.lwe_not(c))
+
+
+@pytest.mark.parametrize("shape", [0, 1, 2])
+def test_every_tile_shape_is_bit_identical(torch_cuda, shape):
+    """The GEMM tile shapes only change speed: outputs of every shape equal
+    the oracle's (C1 gates) and each other's (C2 partial rotation)."""
+    K, ctx = helpers.gpu_world("C1")
+    types, m1, m2 = mi.gate_batch(70, seed=12)
+    c1, c2 = _workload(K, types, m1, m2, seed=120)
+    ctx.set_tiles(shape, shape)
+    try:
+        got = _gates_on_gpu(torch_cuda, ctx, types, c1, c2, 1)
+    finally:
+        ctx.set_tiles(-1, -1)
+    assert np.array_equal(got, helpers.oracle_gates("C1", types, c1, c2))
+    K2, ctx2 = helpers.gpu_world("C2")
+    P = K2.params
+    abar = np.random.default_rng(9).integers(0, 2 * P.N, (200, P.lwe_words)).astype(np.uint32)
+    d = torch_cuda.device("cuda:0")
+    ta = torch_cuda.from_numpy(abar.view(np.int32)).to(d)
+    outs = []
+    for sh in (0, shape):
+        acc = torch_cuda.zeros((200, (P.k + 1) * P.N), dtype=torch_cuda.int32, device=d)
+        ctx2.set_tiles(sh, sh)
+        try:
+            ctx2.blind_rotate(ta, acc, max_steps=600, path=1)   # crosses into party 1
+        finally:
+            ctx2.set_tiles(-1, -1)
+        torch_cuda.cuda.synchronize()
+        outs.append(acc.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_autotune_picks_valid_shapes(torch_cuda):
+    K, ctx = helpers.gpu_world("C1")
+    v1, v2, ms = ctx.autotune(300)
+    assert v1 in (0, 1, 2) and v2 in (0, 1, 2)
+    assert ctx.get_tiles(300) == (v1, v2)
+    assert all(m > 0 for m in ms)
+    types, m1, m2 = mi.gate_batch(300, seed=13)
+    c1, c2 = _workload(K, types, m1, m2, seed=130)
+    got = _gates_on_gpu(torch_cuda, ctx, types, c1, c2, 1)
+    ref = helpers.oracle_gates("C1", types, c1, c2, idx=[0, 150, 299])
+    assert np.array_equal(got[[0, 150, 299]], ref)

@@ -101,3 +101,18 @@ def test_error_codes():
     with pytest.raises(mk.MkError) as e:        # no keys: upload refused on the host
         ctx.upload(stream=0)
     assert e.value.code == -4
+
+
+def test_tile_shape_arguments():
+    import paper_2205_05825_amd as mk
+    ctx = mk.Context(helpers.lib_params(OP.C1), 3)
+    assert ctx.get_tiles(1000) == (0, 0)
+    ctx.set_tiles(2, 1)
+    assert ctx.get_tiles(1000) == (2, 1)
+    ctx.set_tiles(-1, -1)
+    assert ctx.get_tiles(1000) == (0, 0)
+    with pytest.raises(mk.MkError):
+        ctx.set_tiles(3, 0)
+    with pytest.raises(mk.MkError) as e:      # needs the uploaded key
+        ctx.autotune(64, stream=0)
+    assert e.value.code == -4
