@@ -248,15 +248,18 @@ int mk_get_profile(mk_ctx *ctx, double *ms, int64_t *launches, int reset);
 
 /* Tile shapes of the int8-MFMA rotation's two GEMM kernels: 0 = 64 rows x
  * 32 gates per wave (two waves per SIMD), 1 = 128 rows x 32 gates, 2 = 64
- * rows x 64 gates (one wave per SIMD).  Results are identical for every
- * shape; only speed differs.
+ * rows x 64 gates (one wave per SIMD), 3 and 4 = shapes 0 and 1 with each
+ * K-block's key tiles loaded once per workgroup into LDS.  Results are
+ * identical for every shape; only speed differs.
  *   mk_autotune   times every shape of both kernels on the scratch buffers of
  *                 a batch of `count` gates (synchronous on `stream`) and
  *                 records the fastest for that batch size; ms (optional,
- *                 6 floats) receives the average times, gemm1 shapes first.
+ *                 2 * MK_TILE_SHAPES floats) receives the average times,
+ *                 gemm1 shapes first (0 for shapes that do not divide N/32).
  *   mk_set_tiles  forces shapes (-1 = use the tuned or default shape).
  *   mk_get_tiles  reports the shapes a batch of `count` gates would use.
  * Errors: MK_EINVAL, MK_ESTATE (key not uploaded), MK_ENOMEM, MK_EDEVICE. */
+#define MK_TILE_SHAPES 5
 int mk_autotune(mk_ctx *ctx, size_t count, void *stream, int32_t *gemm1_shape,
                 int32_t *gemm2_shape, float *ms);
 int mk_set_tiles(mk_ctx *ctx, int gemm1_shape, int gemm2_shape);

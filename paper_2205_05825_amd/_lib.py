@@ -26,6 +26,7 @@ _L = ctypes.CDLL(LIB_PATH)
 
 MK_OK, MK_EINVAL, MK_ENOMEM, MK_EDEVICE, MK_ESTATE, MK_EPARAM = 0, -1, -2, -3, -4, -5
 PATH_I32, PATH_MFMA_I8 = 0, 1
+TILE_SHAPES = 5
 NAND, AND, OR, NOR, XOR, XNOR, NOT = 0, 1, 2, 3, 4, 5, 6
 
 
@@ -202,9 +203,9 @@ class Context:
     # ---- tile shapes of the MFMA rotation ----
     def autotune(self, count: int, stream=None):
         """Times every GEMM tile shape for batches of `count` gates, keeps the
-        fastest; returns (gemm1 shape, gemm2 shape, ms[6])."""
+        fastest; returns (gemm1 shape, gemm2 shape, ms[2 * TILE_SHAPES])."""
         v1, v2 = ctypes.c_int32(), ctypes.c_int32()
-        ms = (ctypes.c_float * 6)()
+        ms = (ctypes.c_float * (2 * TILE_SHAPES))()
         _check(_L.mk_autotune(self._h, count, _stream(stream), ctypes.byref(v1), ctypes.byref(v2), ms))
         return v1.value, v2.value, list(ms)
 

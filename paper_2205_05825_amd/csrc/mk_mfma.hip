@@ -325,6 +325,69 @@ __device__ __forceinline__ void toeplitz_gemm(const int8_t *A,  // [4][ND][1024]
     }
 }
 
+// The same contraction for a workgroup whose four waves share the row block
+// and the key polynomial (one 32-gate tile per wave): the new diagonal tile
+// of each K-block is loaded once per workgroup, limb t by wave t, into a
+// three-slot LDS ring and read from there by every wave, which cuts the
+// vector-memory traffic per MFMA by 2.5x.  One barrier per K-block: slot
+// kb%3 receives the tiles of K-block kb+3 after every wave has read it as
+// K-block kb's tiles in the previous iteration.  All four waves must call
+// this (gate tiles beyond the batch read zeros through their descriptor).
+template <int MR>
+__device__ __forceinline__ void toeplitz_gemm_lds(const int8_t *A, const int8_t *B, int nc_valid,
+                                                  int NB, int mb0, int lane, int wave,
+                                                  int8_t *lds,  // 3 slots x 4 tiles x 1 KB
+                                                  v16i (&acc)[MR][1][4]) {
+    const int ND = 2 * NB - 1;
+    const __amdgpu_buffer_rsrc_t ra =
+        __builtin_amdgcn_make_buffer_rsrc((void *)A, (short)0, 4 * ND * kTileBytes, kBufWord3);
+    const __amdgpu_buffer_rsrc_t rb =
+        __builtin_amdgcn_make_buffer_rsrc((void *)B, (short)0, nc_valid * NB * kTileBytes, kBufWord3);
+    auto ldA = [&](int t, int kb) {
+        return (v4i)__builtin_amdgcn_raw_buffer_load_b128(
+            ra, (t * ND + mb0 - kb + NB - 1) * kTileBytes + lane * 16, 0, 0);
+    };
+    auto ldB = [&](int kb) {
+        return (v4i)__builtin_amdgcn_raw_buffer_load_b128(rb, kb * kTileBytes + lane * 16, 0, 0);
+    };
+    auto slot = [&](int kb, int t) {
+        return reinterpret_cast<v4i *>(lds + (((kb % 3) * 4 + t) * 64 + lane) * 16);
+    };
+    v4i win[MR][4];
+#pragma unroll
+    for (int r = 0; r < MR; ++r)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) win[r][t] = ldA(t, -r);
+    v4i b = ldB(0);
+    v4i pb0 = ldB(NB > 1 ? 1 : 0), pb1 = ldB(NB > 2 ? 2 : NB - 1);
+    *slot(1, wave) = ldA(wave, NB > 1 ? 1 : 0);
+    *slot(2, wave) = ldA(wave, NB > 2 ? 2 : NB - 1);
+    __syncthreads();
+    auto step = [&](int kb, v4i &pb) {
+        const int kf = kb + 3 < NB ? kb + 3 : NB - 1;
+        const v4i ta = ldA(wave, kf);        // lands in slot kb%3 after the MFMAs
+#pragma unroll
+        for (int r = 0; r < MR; ++r)
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                acc[r][0][t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(win[r][t], b, acc[r][0][t], 0, 0, 0);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+#pragma unroll
+            for (int r = MR - 1; r > 0; --r) win[r][t] = win[r - 1][t];
+            win[0][t] = *slot(kb + 1, t);
+        }
+        b = pb;
+        pb = ldB(kb + 3 < NB ? kb + 3 : NB - 1);
+        *slot(kb, wave) = ta;
+        __syncthreads();
+    };
+    for (int kb = 0; kb < NB; kb += 2) {  // NB is even
+        step(kb, pb0);
+        step(kb + 1, pb1);
+    }
+}
+
 // Recombines the limbs of output register e of row tile r, gate tile c.
 template <int MR, int NC>
 __device__ __forceinline__ uint32_t combine(const v16i (&acc)[MR][NC][4], int r, int c, int e) {
@@ -397,12 +460,13 @@ __device__ __forceinline__ void store_tiles(uint32_t *base, size_t gate_stride, 
 // Stage 1.  Unit u < live adds c'_u = sum_l T(d_l) U_{u,l} into ACC_u; unit
 // u = live+j writes the partial w_j = sum_l T(b_{j,l}) U_{j,l} to Wp[j].
 // Slots j >= live are identically zero (see launch_br_mfma) and skipped.
-template <int MR, int NC, int OCC>
+template <int MR, int NC, int OCC, bool SHARED>
 __global__ __launch_bounds__(256, OCC) void mfma_gemm1_kernel(MfmaArgs a, int party, int bit, int live) {
+    __shared__ __align__(16) int8_t lds[SHARED ? 3 * 4 * kTileBytes : 16];
     const int N = a.N, NB = N / 32, ND = 2 * NB - 1, K1 = a.k + 1, ell = a.ell;
     const int GT = a.GP / 32;
     const Task tk = decode_task<NC>(GT, NB / MR);
-    if (tk.nc_valid <= 0) return;
+    if (!SHARED && tk.nc_valid <= 0) return;
     const int lane = threadIdx.x & 63;
     const int kind = tk.unit / live, j = tk.unit % live;
     v16i acc[MR][NC][4];
@@ -418,20 +482,26 @@ __global__ __launch_bounds__(256, OCC) void mfma_gemm1_kernel(MfmaArgs a, int pa
             ? a.bk + ((((size_t)party * a.n + bit) * 3 + 0) * ell + l) * poly_tiles
             : a.evk + ((size_t)j * ell + l) * poly_tiles;
         const int8_t *B = a.U + ((size_t)(j * ell + l) * GT + tk.gt0) * NB * kTileBytes;
-        toeplitz_gemm<MR, NC>(A, B, tk.nc_valid, NB, tk.rb * MR, lane, acc);
+        if constexpr (SHARED)
+            toeplitz_gemm_lds<MR>(A, B, tk.nc_valid > 0 ? 1 : 0, NB, tk.rb * MR, lane,
+                                  (int)(threadIdx.x / 64), lds, acc);
+        else
+            toeplitz_gemm<MR, NC>(A, B, tk.nc_valid, NB, tk.rb * MR, lane, acc);
     }
+    if (tk.nc_valid <= 0) return;
     uint32_t *base = kind == 0 ? a.acc + (size_t)j * N : a.W + (size_t)j * a.GP * N;
     const size_t gate_stride = kind == 0 ? (size_t)K1 * N : (size_t)N;
     store_tiles<MR, NC>(base, gate_stride, tk, MR, lane, acc, kind == 0);
 }
 
 // Stage 2.  Unit o: ACC_{o ? 1+party : 0} += sum_l T(f_o,l) V_l.
-template <int MR, int NC, int OCC>
+template <int MR, int NC, int OCC, bool SHARED>
 __global__ __launch_bounds__(256, OCC) void mfma_gemm2_kernel(MfmaArgs a, int party, int bit) {
+    __shared__ __align__(16) int8_t lds[SHARED ? 3 * 4 * kTileBytes : 16];
     const int N = a.N, NB = N / 32, ND = 2 * NB - 1, K1 = a.k + 1, ell = a.ell;
     const int GT = a.GP / 32;
     const Task tk = decode_task<NC>(GT, NB / MR);
-    if (tk.nc_valid <= 0) return;
+    if (!SHARED && tk.nc_valid <= 0) return;
     const int lane = threadIdx.x & 63;
     const int o = tk.unit;
     v16i acc[MR][NC][4];
@@ -445,8 +515,13 @@ __global__ __launch_bounds__(256, OCC) void mfma_gemm2_kernel(MfmaArgs a, int pa
     for (int l = 0; l < ell; ++l) {
         const int8_t *A = a.bk + ((((size_t)party * a.n + bit) * 3 + 1 + o) * ell + l) * poly_tiles;
         const int8_t *B = a.V + ((size_t)l * GT + tk.gt0) * NB * kTileBytes;
-        toeplitz_gemm<MR, NC>(A, B, tk.nc_valid, NB, tk.rb * MR, lane, acc);
+        if constexpr (SHARED)
+            toeplitz_gemm_lds<MR>(A, B, tk.nc_valid > 0 ? 1 : 0, NB, tk.rb * MR, lane,
+                                  (int)(threadIdx.x / 64), lds, acc);
+        else
+            toeplitz_gemm<MR, NC>(A, B, tk.nc_valid, NB, tk.rb * MR, lane, acc);
     }
+    if (tk.nc_valid <= 0) return;
     store_tiles<MR, NC>(a.acc + (size_t)(o == 0 ? 0 : 1 + party) * N, (size_t)K1 * N, tk, MR, lane,
                         acc, true);
 }
@@ -456,40 +531,51 @@ __global__ __launch_bounds__(256, OCC) void mfma_gemm2_kernel(MfmaArgs a, int pa
 struct GemmShape {
     int MR, NC;
 };
-constexpr GemmShape kShapes[] = {{2, 1}, {4, 1}, {2, 2}};
-constexpr int kNumShapes = 3;
+constexpr GemmShape kShapes[] = {{2, 1}, {4, 1}, {2, 2}, {2, 1}, {4, 1}};
+constexpr int kNumShapes = 5;
 
+// Shapes 3 and 4 share each K-block's key tiles through LDS.
 template <int V>
 struct ShapeOf;
-template <> struct ShapeOf<0> { static constexpr int MR = 2, NC = 1, OCC = 2; };
-template <> struct ShapeOf<1> { static constexpr int MR = 4, NC = 1, OCC = 1; };
-template <> struct ShapeOf<2> { static constexpr int MR = 2, NC = 2, OCC = 1; };
+template <> struct ShapeOf<0> { static constexpr int MR = 2, NC = 1, OCC = 2; static constexpr bool SH = false; };
+template <> struct ShapeOf<1> { static constexpr int MR = 4, NC = 1, OCC = 1; static constexpr bool SH = false; };
+template <> struct ShapeOf<2> { static constexpr int MR = 2, NC = 2, OCC = 1; static constexpr bool SH = false; };
+template <> struct ShapeOf<3> { static constexpr int MR = 2, NC = 1, OCC = 2; static constexpr bool SH = true; };
+template <> struct ShapeOf<4> { static constexpr int MR = 4, NC = 1, OCC = 1; static constexpr bool SH = true; };
 
 template <int V>
 static void launch_g1(const MfmaArgs &a, int party, int bit, int live, int GT, int NB, hipStream_t s) {
     using S = ShapeOf<V>;
     const int GG = (GT + kWaves * S::NC - 1) / (kWaves * S::NC);
     const unsigned g = (unsigned)(2 * live * (NB / S::MR) * GG);
-    hipLaunchKernelGGL((mfma_gemm1_kernel<S::MR, S::NC, S::OCC>), dim3(g), dim3(64 * kWaves), 0, s, a,
-                       party, bit, live);
+    hipLaunchKernelGGL((mfma_gemm1_kernel<S::MR, S::NC, S::OCC, S::SH>), dim3(g), dim3(64 * kWaves), 0, s,
+                       a, party, bit, live);
 }
 template <int V>
 static void launch_g2(const MfmaArgs &a, int party, int bit, int GT, int NB, hipStream_t s) {
     using S = ShapeOf<V>;
     const int GG = (GT + kWaves * S::NC - 1) / (kWaves * S::NC);
     const unsigned g = (unsigned)(2 * (NB / S::MR) * GG);
-    hipLaunchKernelGGL((mfma_gemm2_kernel<S::MR, S::NC, S::OCC>), dim3(g), dim3(64 * kWaves), 0, s, a,
-                       party, bit);
+    hipLaunchKernelGGL((mfma_gemm2_kernel<S::MR, S::NC, S::OCC, S::SH>), dim3(g), dim3(64 * kWaves), 0, s,
+                       a, party, bit);
 }
 static void gemm1(int v, const MfmaArgs &a, int party, int bit, int live, int GT, int NB, hipStream_t s) {
-    if (v == 1) launch_g1<1>(a, party, bit, live, GT, NB, s);
-    else if (v == 2) launch_g1<2>(a, party, bit, live, GT, NB, s);
-    else launch_g1<0>(a, party, bit, live, GT, NB, s);
+    switch (v) {
+        case 1: launch_g1<1>(a, party, bit, live, GT, NB, s); break;
+        case 2: launch_g1<2>(a, party, bit, live, GT, NB, s); break;
+        case 3: launch_g1<3>(a, party, bit, live, GT, NB, s); break;
+        case 4: launch_g1<4>(a, party, bit, live, GT, NB, s); break;
+        default: launch_g1<0>(a, party, bit, live, GT, NB, s);
+    }
 }
 static void gemm2(int v, const MfmaArgs &a, int party, int bit, int GT, int NB, hipStream_t s) {
-    if (v == 1) launch_g2<1>(a, party, bit, GT, NB, s);
-    else if (v == 2) launch_g2<2>(a, party, bit, GT, NB, s);
-    else launch_g2<0>(a, party, bit, GT, NB, s);
+    switch (v) {
+        case 1: launch_g2<1>(a, party, bit, GT, NB, s); break;
+        case 2: launch_g2<2>(a, party, bit, GT, NB, s); break;
+        case 3: launch_g2<3>(a, party, bit, GT, NB, s); break;
+        case 4: launch_g2<4>(a, party, bit, GT, NB, s); break;
+        default: launch_g2<0>(a, party, bit, GT, NB, s);
+    }
 }
 
 __global__ void mfma_copyout_kernel(const uint32_t *__restrict__ src, uint32_t *__restrict__ dst,
@@ -616,7 +702,7 @@ int autotune(mk_ctx *ctx, size_t count, hipStream_t s, int *v1_out, int *v2_out,
     MK_HIP(hipEventCreate(&e0), "autotune event");
     MK_HIP(hipEventCreate(&e1), "autotune event");
     constexpr int kReps = 4;
-    float best[2] = {1e30f, 1e30f};
+    float best[2] = {3.0e38f, 3.0e38f};
     int pick[2] = {0, 0};
     for (int which = 0; which < 2; ++which)
         for (int v = 0; v < kNumShapes; ++v) {

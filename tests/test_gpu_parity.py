@@ -185,7 +185,7 @@ def test_not_gate(torch_cuda):
     assert np.array_equal(out.cpu().numpy().view(np.uint32), tfhe.lwe_not(c))
 
 
-@pytest.mark.parametrize("shape", [0, 1, 2])
+@pytest.mark.parametrize("shape", [0, 1, 2, 3, 4])
 def test_every_tile_shape_is_bit_identical(torch_cuda, shape):
     """The GEMM tile shapes only change speed: outputs of every shape equal
     the oracle's (C1 gates) and each other's (C2 partial rotation)."""
@@ -219,9 +219,9 @@ def test_every_tile_shape_is_bit_identical(torch_cuda, shape):
 def test_autotune_picks_valid_shapes(torch_cuda):
     K, ctx = helpers.gpu_world("C1")
     v1, v2, ms = ctx.autotune(300)
-    assert v1 in (0, 1, 2) and v2 in (0, 1, 2)
+    assert v1 in range(5) and v2 in range(5)
     assert ctx.get_tiles(300) == (v1, v2)
-    assert all(m > 0 for m in ms)
+    assert all(m > 0 for m in ms)     # N/32 = 8 admits every shape
     types, m1, m2 = mi.gate_batch(300, seed=13)
     c1, c2 = _workload(K, types, m1, m2, seed=130)
     got = _gates_on_gpu(torch_cuda, ctx, types, c1, c2, 1)

@@ -112,7 +112,7 @@ def test_tile_shape_arguments():
     ctx.set_tiles(-1, -1)
     assert ctx.get_tiles(1000) == (0, 0)
     with pytest.raises(mk.MkError):
-        ctx.set_tiles(3, 0)
+        ctx.set_tiles(5, 0)
     with pytest.raises(mk.MkError) as e:      # needs the uploaded key
         ctx.autotune(64, stream=0)
     assert e.value.code == -4
