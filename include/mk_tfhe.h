@@ -246,11 +246,13 @@ int mk_build_lr_step(int m, int d, int shift, mk_gate *gates, int32_t *n_gates,
 int mk_set_profiling(mk_ctx *ctx, int level);
 int mk_get_profile(mk_ctx *ctx, double *ms, int64_t *launches, int reset);
 
-/* Tile shapes of the int8-MFMA rotation's two GEMM kernels: 0 = 64 rows x
- * 32 gates per wave (two waves per SIMD), 1 = 128 rows x 32 gates, 2 = 64
- * rows x 64 gates (one wave per SIMD), 3 and 4 = shapes 0 and 1 with each
- * K-block's key tiles loaded once per workgroup into LDS.  Results are
- * identical for every shape; only speed differs.
+/* Tile shapes of the int8-MFMA rotation's two GEMM kernels.  Limb-split
+ * shapes, where a workgroup's four waves hold the four key limbs of one
+ * output block: 0 = 256 rows x 32 gates, 1 = 128 rows x 64 gates, 2 = 128
+ * rows x 32 gates, 4 = 256 rows x 64 gates; shape 3 = one wave per 64 rows
+ * x 32 gates with all four limbs.  Results are identical for every shape;
+ * only speed differs.  Without tuning the first shape whose row count
+ * divides N is used.
  *   mk_autotune   times every shape of both kernels on the scratch buffers of
  *                 a batch of `count` gates (synchronous on `stream`) and
  *                 records the fastest for that batch size; ms (optional,

@@ -48,6 +48,9 @@ C1B = Params(k=2, n=64, N=256, bk_ell=2, ks_t=6,
 # C1B shape with 4 parties.
 C1B4 = Params(k=4, n=64, N=256, bk_ell=2, ks_t=6,
               bk_noise_log2=26, ks_noise_log2=20, lwe_noise_log2=12)
+# Smallest ring the int8-MFMA path takes (N/32 = 4 K-blocks), parity only.
+C1S = Params(k=2, n=32, N=128, bk_ell=2, ks_t=6,
+             bk_noise_log2=26, ks_noise_log2=20, lwe_noise_log2=12)
 # Table 7 shape with 2 parties.
 C2 = Params(k=2, n=560, N=1024, bk_ell=3, ks_t=8,
             bk_noise_log2=30, ks_noise_log2=15, lwe_noise_log2=15)

@@ -242,157 +242,153 @@ __global__ __launch_bounds__(256) void mfma_wdec_kernel(MfmaArgs a, int live) {
                  kg * kDigKB);
 }
 
-// Accumulates acc[r][t] += T_t(A)[rows of tile mb0+r] * B over all NB
-// K-blocks, for the 4 limbs t.  The Toeplitz tile of (row tile mb, K-block
-// kb) is diagonal tile mb - kb, so when kb advances every row tile inherits
-// the previous tile of the row tile above it and only row tile 0 needs a new
-// one: a register window of MR tiles per limb, one new tile per limb per
-// K-block.  Loads run two K-blocks ahead of the MFMAs (a two-slot ring,
-// unrolled so that every register index is static).  They are buffer loads:
-// the descriptors bound every access to the operand blocks (out-of-range
-// reads return 0), and, unlike plain loads, the compiler does not merge the
-// ring's loop-carried loads back into a load at the point of use.
+// ------------------------------------------------------------- GEMMs ----
+//
+// A wave computes MR row tiles (32 output coefficients each) of NC gate
+// tiles: acc[r][c][t] accumulates sum_l T_t(A_l) B_l over the ell key
+// polynomials A_l and the NB K-blocks, for the 4 limbs t.  The Toeplitz
+// tile at (row tile mb, K-block kb) is diagonal tile mb - kb.
+//
+// Skewed schedule: at step x, row tile r works on K-block x + r, whose tile
+// is diagonal mb0 - x =: s(x) for every r, so all MR row tiles share one key
+// tile per limb per step and the digit tiles slide past them instead.  For
+// each l the steps run x = -(MR-1) .. NB-1 (P = NB + MR - 1 steps); a row
+// tile whose K-block lies outside [0, NB) meets a digit tile that reads as
+// zero.  Flattened over l, step X = l P + y (y = x + MR - 1) loads the key
+// tiles alpha(X) = s_l(x) and the digit tiles beta(X) = B_l[K-block y] (zero
+// for y >= NB), and row tile r multiplies alpha(X) by beta(X - MR + 1 + r):
+// the stream is uniform across the l boundaries (the MR - 1 zero digit tiles
+// at the end of each l are exactly what the first steps of the next l see),
+// so the load pipeline never drains between key polynomials.
+//
+// Loads are buffer loads through wave-uniform descriptors: accesses are
+// bounded by the operand blocks, reads out of range return 0 (used for the
+// zero tiles), and, unlike plain loads, the compiler does not merge the
+// rings' loads back into a load at the point of use.
 constexpr uint32_t kBufWord3 = 0x00020000u;  // raw dword buffer, gfx9 family
+constexpr uint32_t kOutOfRange = 0x80000000u;  // offset beyond every block
 
-template <int MR, int NC>
-__device__ __forceinline__ void toeplitz_gemm(const int8_t *A,  // [4][ND][1024]
-                                              const int8_t *B,  // NC x [NB][1024], contiguous
-                                              int nc_valid, int NB, int mb0, int lane,
-                                              v16i (&acc)[MR][NC][4]) {
-    const int ND = 2 * NB - 1;
-    const __amdgpu_buffer_rsrc_t ra =
-        __builtin_amdgcn_make_buffer_rsrc((void *)A, (short)0, 4 * ND * kTileBytes, kBufWord3);
-    // gate tiles beyond nc_valid (ragged last group) read as zero
-    const __amdgpu_buffer_rsrc_t rb =
-        __builtin_amdgcn_make_buffer_rsrc((void *)B, (short)0, nc_valid * NB * kTileBytes, kBufWord3);
-    auto ldA = [&](int t, int kb) {
-        return (v4i)__builtin_amdgcn_raw_buffer_load_b128(
-            ra, (t * ND + mb0 - kb + NB - 1) * kTileBytes + lane * 16, 0, 0);
-    };
-    auto ldB = [&](int c, int kb) {
-        return (v4i)__builtin_amdgcn_raw_buffer_load_b128(
-            rb, (c * NB + kb) * kTileBytes + lane * 16, 0, 0);
-    };
-    v4i win[MR][4];
-#pragma unroll
-    for (int r = 0; r < MR; ++r)
-#pragma unroll
-        for (int t = 0; t < 4; ++t) win[r][t] = ldA(t, -r);
-    v4i b[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) b[c] = ldB(c, 0);
-    // ring slot s holds the operands of K-block kb+1 (s = kb & 1)
-    v4i pa0[4], pa1[4], pb0[NC], pb1[NC];
-    {
-        const int k1 = NB > 1 ? 1 : 0, k2 = NB > 2 ? 2 : NB - 1;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            pa0[t] = ldA(t, k1);
-            pa1[t] = ldA(t, k2);
-        }
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            pb0[c] = ldB(c, k1);
-            pb1[c] = ldB(c, k2);
-        }
+struct Operands {
+    const int8_t *A;   // [ell][4][ND][1024] key tiles
+    const int8_t *B;   // digit tiles of l = 0 and the wave's first gate tile
+    uint32_t b_poly;   // bytes between the digit tiles of consecutive l
+    int ell, NB, mb0, nc_valid;
+};
+
+// Position in the flattened step stream: (l, y) and the byte offsets of
+// limb 0 of alpha and of gate tile 0 of beta there.  Advancing is
+// branch-free (masks, not conditionals), so the compiler keeps every load of
+// the unrolled loop in one basic block and its load counters exact.
+struct Cursor {
+    int l, y;
+    uint32_t a, b;
+};
+
+// Digit K-block of step y is y - dshift (0 for the skewed schedule, MR - 1
+// for the windowed one); K-blocks outside [0, NB) read as zero.
+struct Streams {
+    __amdgpu_buffer_rsrc_t ra, rb;
+    int ell, NB, ND, P, MRm1, nc_valid, dshift;
+    uint32_t lane16, a_wrap, b_wrap, limb_stride, tile_stride, b_poly, mb0;
+    __device__ __forceinline__ Streams(const Operands &o, int MR, int lane, int dshift_) {
+        ell = o.ell; NB = o.NB; ND = 2 * NB - 1; P = NB + MR - 1; MRm1 = MR - 1; dshift = dshift_;
+        nc_valid = o.nc_valid; lane16 = (uint32_t)lane * 16; b_poly = o.b_poly; mb0 = (uint32_t)o.mb0;
+        limb_stride = (uint32_t)ND * kTileBytes;
+        tile_stride = (uint32_t)NB * kTileBytes;
+        // offset change from (l, P-1) to (l+1, 0) beyond the usual step
+        a_wrap = (uint32_t)(4 * ND + P) * kTileBytes;
+        b_wrap = b_poly - (uint32_t)P * kTileBytes;
+        ra = __builtin_amdgcn_make_buffer_rsrc((void *)o.A, (short)0, ell * 4 * ND * kTileBytes, kBufWord3);
+        const int nv = nc_valid > 0 ? nc_valid : 0;
+        rb = __builtin_amdgcn_make_buffer_rsrc((void *)o.B, (short)0,
+                                               (int)((ell - 1) * b_poly + nv * NB * kTileBytes), kBufWord3);
     }
-    auto step = [&](int kb, v4i (&pa)[4], v4i (&pb)[NC]) {
+    __device__ __forceinline__ Cursor at(int X) const {  // setup only (divides)
+        Cursor q;
+        q.l = X / P;
+        q.y = X - q.l * P;
+        q.a = (uint32_t)((4 * q.l * ND + (int)mb0 - (q.y - MRm1) + NB - 1) * kTileBytes);
+        q.b = (uint32_t)q.l * b_poly + (uint32_t)((q.y - dshift) * kTileBytes);
+        return q;
+    }
+    __device__ __forceinline__ void next(Cursor &q) const {
+        q.y += 1;
+        q.a -= kTileBytes;
+        q.b += kTileBytes;
+        const uint32_t w = 0u - (uint32_t)(q.y == P);  // all ones at a wrap
+        q.y &= ~(int)w;
+        q.l += (int)(w & 1u);
+        q.a += a_wrap & w;
+        q.b += b_wrap & w;
+    }
+    // limb t of alpha at q (zero past the last polynomial); the selects are
+    // on uniform values (scalar), the lane offset is added last
+    __device__ __forceinline__ v4i key(const Cursor &q, int t) const {
+        const uint32_t uni = q.l < ell ? q.a + t * limb_stride : kOutOfRange;
+        return (v4i)__builtin_amdgcn_raw_buffer_load_b128(ra, uni + lane16, 0, 0);
+    }
+    // gate tile c of beta at q (zero outside the K-blocks, past the last
+    // polynomial and for gate tiles beyond the batch)
+    __device__ __forceinline__ v4i digits(const Cursor &q, int c) const {
+        const bool valid = (unsigned)(q.y - dshift) < (unsigned)NB && q.l < ell && c < nc_valid;
+        const uint32_t uni = valid ? q.b + c * tile_stride : kOutOfRange;
+        return (v4i)__builtin_amdgcn_raw_buffer_load_b128(rb, uni + lane16, 0, 0);
+    }
+};
+
+// Register rings of R = MR + D slots (D = max(MR, 2) steps of prefetch):
+// alpha(X) and beta(X) live in slot X mod R.  The loop is unrolled R times
+// so that every slot index is a compile-time constant (no register moves);
+// after step X's MFMAs the slots of alpha(X - MR + 1) and beta(X - MR + 1),
+// no longer needed, receive alpha(X + D + 1) and beta(X + D + 1).
+template <int MR, int NC, class Init>
+__device__ __forceinline__ void toeplitz_gemm(const Operands &o, int lane, v16i (&acc)[MR][NC][4],
+                                              Init init) {
+    constexpr int D = MR > 2 ? MR : 2, R = MR + D;
+    const Streams S(o, MR, lane, 0);
+    const int steps = o.ell * S.P;
+    v4i sa[R][4], sb[R][NC];
+#pragma unroll
+    for (int i = 1; i < MR; ++i)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) sb[R - i][c] = v4i{};  // beta(-i) = 0
+    Cursor q = S.at(0);
+#pragma unroll
+    for (int x = 0; x <= D; ++x) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) sa[x][t] = S.key(q, t);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) sb[x][c] = S.digits(q, c);
+        S.next(q);
+        __builtin_amdgcn_sched_barrier(0);  // issue in ring order
+    }
+    init();  // sets acc, once the prologue's loads are in flight
+    auto step = [&](int u) {  // u = X mod R
 #pragma unroll
         for (int r = 0; r < MR; ++r)
 #pragma unroll
             for (int c = 0; c < NC; ++c)
 #pragma unroll
                 for (int t = 0; t < 4; ++t)
-                    acc[r][c][t] =
-                        __builtin_amdgcn_mfma_i32_32x32x32_i8(win[r][t], b[c], acc[r][c][t], 0, 0, 0);
+                    acc[r][c][t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                        sa[u][t], sb[(u - MR + 1 + r + R) % R][c], acc[r][c][t], 0, 0, 0);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
+        for (int t = 0; t < 4; ++t) sa[(u + D + 1) % R][t] = S.key(q, t);
 #pragma unroll
-            for (int r = MR - 1; r > 0; --r) win[r][t] = win[r - 1][t];
-            win[0][t] = pa[t];
-        }
-#pragma unroll
-        for (int c = 0; c < NC; ++c) b[c] = pb[c];
-        const int kf = kb + 3 < NB ? kb + 3 : NB - 1;  // clamped: stays in range
-#pragma unroll
-        for (int t = 0; t < 4; ++t) pa[t] = ldA(t, kf);
-#pragma unroll
-        for (int c = 0; c < NC; ++c) pb[c] = ldB(c, kf);
+        for (int c = 0; c < NC; ++c) sb[(u + D + 1) % R][c] = S.digits(q, c);
+        S.next(q);
+        // keep the scheduler from sinking these loads towards their use
+        __builtin_amdgcn_sched_barrier(0);
     };
-    for (int kb = 0; kb < NB; kb += 2) {  // NB is even (N >= 64)
-        step(kb, pa0, pb0);
-        step(kb + 1, pa1, pb1);
+    // branch-free main loop (keeps the load counters exact), then the tail
+    int X = 0;
+    for (; X + R <= steps; X += R) {
+#pragma unroll
+        for (int u = 0; u < R; ++u) step(u);
     }
-}
-
-// The same contraction for a workgroup whose four waves share the row block
-// and the key polynomial (one 32-gate tile per wave): the new diagonal tile
-// of each K-block is loaded once per workgroup, limb t by wave t, into a
-// three-slot LDS ring and read from there by every wave, which cuts the
-// vector-memory traffic per MFMA by 2.5x.  One barrier per K-block: slot
-// kb%3 receives the tiles of K-block kb+3 after every wave has read it as
-// K-block kb's tiles in the previous iteration.  All four waves must call
-// this (gate tiles beyond the batch read zeros through their descriptor).
-template <int MR>
-__device__ __forceinline__ void toeplitz_gemm_lds(const int8_t *A, const int8_t *B, int nc_valid,
-                                                  int NB, int mb0, int lane, int wave,
-                                                  int8_t *lds,  // 3 slots x 4 tiles x 1 KB
-                                                  v16i (&acc)[MR][1][4]) {
-    const int ND = 2 * NB - 1;
-    const __amdgpu_buffer_rsrc_t ra =
-        __builtin_amdgcn_make_buffer_rsrc((void *)A, (short)0, 4 * ND * kTileBytes, kBufWord3);
-    const __amdgpu_buffer_rsrc_t rb =
-        __builtin_amdgcn_make_buffer_rsrc((void *)B, (short)0, nc_valid * NB * kTileBytes, kBufWord3);
-    auto ldA = [&](int t, int kb) {
-        return (v4i)__builtin_amdgcn_raw_buffer_load_b128(
-            ra, (t * ND + mb0 - kb + NB - 1) * kTileBytes + lane * 16, 0, 0);
-    };
-    auto ldB = [&](int kb) {
-        return (v4i)__builtin_amdgcn_raw_buffer_load_b128(rb, kb * kTileBytes + lane * 16, 0, 0);
-    };
-    auto slot = [&](int kb, int t) {
-        return reinterpret_cast<v4i *>(lds + (((kb % 3) * 4 + t) * 64 + lane) * 16);
-    };
-    v4i win[MR][4];
 #pragma unroll
-    for (int r = 0; r < MR; ++r)
-#pragma unroll
-        for (int t = 0; t < 4; ++t) win[r][t] = ldA(t, -r);
-    v4i b = ldB(0);
-    v4i pb0 = ldB(NB > 1 ? 1 : 0), pb1 = ldB(NB > 2 ? 2 : NB - 1);
-    *slot(1, wave) = ldA(wave, NB > 1 ? 1 : 0);
-    *slot(2, wave) = ldA(wave, NB > 2 ? 2 : NB - 1);
-    __syncthreads();
-    auto step = [&](int kb, v4i &pb) {
-        const int kf = kb + 3 < NB ? kb + 3 : NB - 1;
-        const v4i ta = ldA(wave, kf);        // lands in slot kb%3 after the MFMAs
-#pragma unroll
-        for (int r = 0; r < MR; ++r)
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-                acc[r][0][t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(win[r][t], b, acc[r][0][t], 0, 0, 0);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-#pragma unroll
-            for (int r = MR - 1; r > 0; --r) win[r][t] = win[r - 1][t];
-            win[0][t] = *slot(kb + 1, t);
-        }
-        b = pb;
-        pb = ldB(kb + 3 < NB ? kb + 3 : NB - 1);
-        *slot(kb, wave) = ta;
-        __syncthreads();
-    };
-    for (int kb = 0; kb < NB; kb += 2) {  // NB is even
-        step(kb, pb0);
-        step(kb + 1, pb1);
-    }
-}
-
-// Recombines the limbs of output register e of row tile r, gate tile c.
-template <int MR, int NC>
-__device__ __forceinline__ uint32_t combine(const v16i (&acc)[MR][NC][4], int r, int c, int e) {
-    return (uint32_t)acc[r][c][0][e] + ((uint32_t)acc[r][c][1][e] << 8) +
-           ((uint32_t)acc[r][c][2][e] << 16) + ((uint32_t)acc[r][c][3][e] << 24);
+    for (int u = 0; u < R - 1; ++u)
+        if (X + u < steps) step(u);
 }
 
 constexpr int kWaves = 4;   // waves per workgroup
@@ -400,8 +396,8 @@ constexpr int kWaves = 4;   // waves per workgroup
 // Task decode shared by both GEMMs.  A wave owns MR row tiles (of 32 rows)
 // of NC consecutive 32-gate tiles; a workgroup's four waves share the row
 // block and the unit (so the key tiles they load are shared through the
-// CU's L1) and cover 4 NC gate tiles.  The gate group is the fastest index:
-// with 8 gate groups each XCD keeps one group's digits in its L2.
+// CU's L1 or LDS) and cover 4 NC gate tiles.  The gate group is the fastest
+// index: with 8 gate groups each XCD keeps one group's digits in its L2.
 struct Task {
     int unit, rb, gt0, nc_valid;
 };
@@ -414,45 +410,93 @@ __device__ __forceinline__ Task decode_task(int GT, int RB) {
     task /= GG;
     t.rb = task % RB;
     t.unit = task / RB;
-    t.gt0 = (gg * kWaves + (int)(threadIdx.x / 64)) * NC;
+    // readfirstlane: the wave index is uniform, so are the operand pointers
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
+    t.gt0 = (gg * kWaves + wave) * NC;
     t.nc_valid = GT - t.gt0 < NC ? GT - t.gt0 : NC;
     return t;
 }
 
-// out[rows of the wave's tiles] (+)= limb-combined accumulators, for the
-// valid gate tiles; `rmw` adds to the old contents.  Registers 4q..4q+3 of
-// row tile r hold rows m..m+3 of one column (gate).
+// Output register e of row tile r, gate tile c holds row 32 (rb MR + r) +
+// 8 (e / 4) + 4 (lane / 32) + e % 4 of gate 32 (gt0 + c) + lane % 32, so
+// registers 4q..4q+3 are four consecutive words of one gate's row.
+template <int MR>
+__device__ __forceinline__ uint32_t *tile_row(uint32_t *base, size_t gate_stride, const Task &tk,
+                                              int c, int r, int lane) {
+    const int g = (tk.gt0 + c) * 32 + (lane & 31);
+    return base + (size_t)g * gate_stride + 32 * (tk.rb * MR + r) + 4 * (lane / 32);
+}
+
+// Read-modify-write without a dependent load at the end: the old output
+// values are loaded before the contraction starts (load_tiles) and become
+// the accumulators' initial values once its first loads are in flight
+// (seed_acc): the low 24 bits go to limb 0's accumulator and the high 8 bits
+// to limb 3's, which keeps every limb sum inside int32 (|sum| < 2^30 by the
+// setup bound) and recombines to the old value plus the product.
+template <int MR, int NC>
+__device__ __forceinline__ void load_tiles(const uint32_t *base, size_t gate_stride, const Task &tk,
+                                           int lane, uint4 (&old)[MR][NC][4]) {
+    // gate tiles beyond the batch (LDS shapes' idle waves) are never stored:
+    // their accumulators start at 0; ragged tiles re-read tile 0
+    if (tk.nc_valid <= 0) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int r = 0; r < MR; ++r)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) old[r][c][q] = make_uint4(0, 0, 0, 0);
+        return;
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int r = 0; r < MR; ++r) {
+            const uint32_t *row = tile_row<MR>(const_cast<uint32_t *>(base), gate_stride, tk,
+                                               c < tk.nc_valid ? c : 0, r, lane);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) old[r][c][q] = *reinterpret_cast<const uint4 *>(row + 8 * q);
+        }
+}
+template <int MR, int NC>
+__device__ __forceinline__ void seed_acc(const uint4 (&old)[MR][NC][4], v16i (&acc)[MR][NC][4]) {
+#pragma unroll
+    for (int r = 0; r < MR; ++r)
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t w[4] = {old[r][c][q].x, old[r][c][q].y, old[r][c][q].z, old[r][c][q].w};
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    acc[r][c][0][4 * q + i] = (int)(w[i] & 0xFFFFFFu);
+                    acc[r][c][3][4 * q + i] = (int)(w[i] >> 24);
+                }
+            }
+}
+
+// Recombines the limbs of output register e of row tile r, gate tile c.
+template <int MR, int NC>
+__device__ __forceinline__ uint32_t combine(const v16i (&acc)[MR][NC][4], int r, int c, int e) {
+    return (uint32_t)acc[r][c][0][e] + ((uint32_t)acc[r][c][1][e] << 8) +
+           ((uint32_t)acc[r][c][2][e] << 16) + ((uint32_t)acc[r][c][3][e] << 24);
+}
+
+// out[rows of the wave's tiles] = limb-combined accumulators, for the valid
+// gate tiles.
 template <int MR, int NC>
 __device__ __forceinline__ void store_tiles(uint32_t *base, size_t gate_stride, const Task &tk,
-                                            int MRrows, int lane, const v16i (&acc)[MR][NC][4],
-                                            bool rmw) {
+                                            int lane, const v16i (&acc)[MR][NC][4]) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         if (c >= tk.nc_valid) break;
-        const int g = (tk.gt0 + c) * 32 + (lane & 31);
-        uint32_t *dst = base + (size_t)g * gate_stride;
 #pragma unroll
         for (int r = 0; r < MR; ++r) {
-            uint32_t *row = dst + 32 * (tk.rb * MRrows + r) + 4 * (lane / 32);
-            uint4 old[4];
-            if (rmw) {
+            uint32_t *row = tile_row<MR>(base, gate_stride, tk, c, r, lane);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) old[q] = *reinterpret_cast<const uint4 *>(row + 8 * q);
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                uint4 v = make_uint4(combine<MR, NC>(acc, r, c, 4 * q + 0),
-                                     combine<MR, NC>(acc, r, c, 4 * q + 1),
-                                     combine<MR, NC>(acc, r, c, 4 * q + 2),
-                                     combine<MR, NC>(acc, r, c, 4 * q + 3));
-                if (rmw) {
-                    v.x += old[q].x;
-                    v.y += old[q].y;
-                    v.z += old[q].z;
-                    v.w += old[q].w;
-                }
-                *reinterpret_cast<uint4 *>(row + 8 * q) = v;
-            }
+            for (int q = 0; q < 4; ++q)
+                *reinterpret_cast<uint4 *>(row + 8 * q) =
+                    make_uint4(combine<MR, NC>(acc, r, c, 4 * q + 0), combine<MR, NC>(acc, r, c, 4 * q + 1),
+                               combine<MR, NC>(acc, r, c, 4 * q + 2), combine<MR, NC>(acc, r, c, 4 * q + 3));
         }
     }
 }
@@ -460,15 +504,23 @@ __device__ __forceinline__ void store_tiles(uint32_t *base, size_t gate_stride, 
 // Stage 1.  Unit u < live adds c'_u = sum_l T(d_l) U_{u,l} into ACC_u; unit
 // u = live+j writes the partial w_j = sum_l T(b_{j,l}) U_{j,l} to Wp[j].
 // Slots j >= live are identically zero (see launch_br_mfma) and skipped.
-template <int MR, int NC, int OCC, bool SHARED>
+template <int MR, int NC, int OCC>
 __global__ __launch_bounds__(256, OCC) void mfma_gemm1_kernel(MfmaArgs a, int party, int bit, int live) {
-    __shared__ __align__(16) int8_t lds[SHARED ? 3 * 4 * kTileBytes : 16];
     const int N = a.N, NB = N / 32, ND = 2 * NB - 1, K1 = a.k + 1, ell = a.ell;
     const int GT = a.GP / 32;
     const Task tk = decode_task<NC>(GT, NB / MR);
-    if (!SHARED && tk.nc_valid <= 0) return;
+    if (tk.nc_valid <= 0) return;
     const int lane = threadIdx.x & 63;
     const int kind = tk.unit / live, j = tk.unit % live;
+    const size_t poly_tiles = (size_t)4 * ND * kTileBytes;
+    Operands o;
+    o.A = kind == 0 ? a.bk + (((size_t)party * a.n + bit) * 3 + 0) * ell * poly_tiles
+                    : a.evk + (size_t)j * ell * poly_tiles;
+    o.B = a.U + ((size_t)j * ell * GT + tk.gt0) * NB * kTileBytes;
+    o.b_poly = (uint32_t)((size_t)GT * NB * kTileBytes);
+    o.ell = ell; o.NB = NB; o.mb0 = tk.rb * MR; o.nc_valid = tk.nc_valid;
+    uint32_t *base = kind == 0 ? a.acc + (size_t)j * N : a.W + (size_t)j * a.GP * N;
+    const size_t gate_stride = kind == 0 ? (size_t)K1 * N : (size_t)N;
     v16i acc[MR][NC][4];
 #pragma unroll
     for (int r = 0; r < MR; ++r)
@@ -476,34 +528,31 @@ __global__ __launch_bounds__(256, OCC) void mfma_gemm1_kernel(MfmaArgs a, int pa
         for (int c = 0; c < NC; ++c)
 #pragma unroll
             for (int t = 0; t < 4; ++t) acc[r][c][t] = v16i{};
-    const size_t poly_tiles = (size_t)4 * ND * kTileBytes;
-    for (int l = 0; l < ell; ++l) {
-        const int8_t *A = kind == 0
-            ? a.bk + ((((size_t)party * a.n + bit) * 3 + 0) * ell + l) * poly_tiles
-            : a.evk + ((size_t)j * ell + l) * poly_tiles;
-        const int8_t *B = a.U + ((size_t)(j * ell + l) * GT + tk.gt0) * NB * kTileBytes;
-        if constexpr (SHARED)
-            toeplitz_gemm_lds<MR>(A, B, tk.nc_valid > 0 ? 1 : 0, NB, tk.rb * MR, lane,
-                                  (int)(threadIdx.x / 64), lds, acc);
-        else
-            toeplitz_gemm<MR, NC>(A, B, tk.nc_valid, NB, tk.rb * MR, lane, acc);
+    if (kind == 0) {  // c'_j is added to ACC_j
+        uint4 old[MR][NC][4];
+        load_tiles<MR, NC>(base, gate_stride, tk, lane, old);
+        toeplitz_gemm<MR, NC>(o, lane, acc, [&]() { seed_acc<MR, NC>(old, acc); });
+    } else {
+        toeplitz_gemm<MR, NC>(o, lane, acc, []() {});
     }
-    if (tk.nc_valid <= 0) return;
-    uint32_t *base = kind == 0 ? a.acc + (size_t)j * N : a.W + (size_t)j * a.GP * N;
-    const size_t gate_stride = kind == 0 ? (size_t)K1 * N : (size_t)N;
-    store_tiles<MR, NC>(base, gate_stride, tk, MR, lane, acc, kind == 0);
+    store_tiles<MR, NC>(base, gate_stride, tk, lane, acc);
 }
 
 // Stage 2.  Unit o: ACC_{o ? 1+party : 0} += sum_l T(f_o,l) V_l.
-template <int MR, int NC, int OCC, bool SHARED>
+template <int MR, int NC, int OCC>
 __global__ __launch_bounds__(256, OCC) void mfma_gemm2_kernel(MfmaArgs a, int party, int bit) {
-    __shared__ __align__(16) int8_t lds[SHARED ? 3 * 4 * kTileBytes : 16];
     const int N = a.N, NB = N / 32, ND = 2 * NB - 1, K1 = a.k + 1, ell = a.ell;
     const int GT = a.GP / 32;
     const Task tk = decode_task<NC>(GT, NB / MR);
-    if (!SHARED && tk.nc_valid <= 0) return;
+    if (tk.nc_valid <= 0) return;
     const int lane = threadIdx.x & 63;
-    const int o = tk.unit;
+    const size_t poly_tiles = (size_t)4 * ND * kTileBytes;
+    Operands o;
+    o.A = a.bk + ((((size_t)party * a.n + bit) * 3 + 1 + tk.unit) * ell) * poly_tiles;
+    o.B = a.V + (size_t)tk.gt0 * NB * kTileBytes;
+    o.b_poly = (uint32_t)((size_t)GT * NB * kTileBytes);
+    o.ell = ell; o.NB = NB; o.mb0 = tk.rb * MR; o.nc_valid = tk.nc_valid;
+    uint32_t *base = a.acc + (size_t)(tk.unit == 0 ? 0 : 1 + party) * N;
     v16i acc[MR][NC][4];
 #pragma unroll
     for (int r = 0; r < MR; ++r)
@@ -511,53 +560,281 @@ __global__ __launch_bounds__(256, OCC) void mfma_gemm2_kernel(MfmaArgs a, int pa
         for (int c = 0; c < NC; ++c)
 #pragma unroll
             for (int t = 0; t < 4; ++t) acc[r][c][t] = v16i{};
-    const size_t poly_tiles = (size_t)4 * ND * kTileBytes;
-    for (int l = 0; l < ell; ++l) {
-        const int8_t *A = a.bk + ((((size_t)party * a.n + bit) * 3 + 1 + o) * ell + l) * poly_tiles;
-        const int8_t *B = a.V + ((size_t)l * GT + tk.gt0) * NB * kTileBytes;
-        if constexpr (SHARED)
-            toeplitz_gemm_lds<MR>(A, B, tk.nc_valid > 0 ? 1 : 0, NB, tk.rb * MR, lane,
-                                  (int)(threadIdx.x / 64), lds, acc);
-        else
-            toeplitz_gemm<MR, NC>(A, B, tk.nc_valid, NB, tk.rb * MR, lane, acc);
-    }
-    if (tk.nc_valid <= 0) return;
-    store_tiles<MR, NC>(a.acc + (size_t)(o == 0 ? 0 : 1 + party) * N, (size_t)K1 * N, tk, MR, lane,
-                        acc, true);
+    uint4 old[MR][NC][4];
+    load_tiles<MR, NC>(base, (size_t)K1 * N, tk, lane, old);
+    toeplitz_gemm<MR, NC>(o, lane, acc, [&]() { seed_acc<MR, NC>(old, acc); });
+    store_tiles<MR, NC>(base, (size_t)K1 * N, tk, lane, acc);
 }
 
-// Tile configurations of the two GEMMs (rows per wave MR x gate tiles per
-// wave NC, waves per SIMD OCC).  The autotuner picks one per batch shape.
+// ---------------------------------------------------- limb-split GEMMs ----
+//
+// The workgroup's four waves compute the four limb products of the same MR
+// row tiles x NC gate tiles: wave t accumulates S_t = sum_l T_t(A_l) B_l
+// (one accumulator tile per row tile and gate tile) and the limbs are
+// combined, sum_t 2^(8t) S_t, through LDS at the end.  Per step a wave
+// loads one key tile and NC digit tiles for MR NC MFMAs; the digit tiles
+// are shared by the four waves through the CU's L1.
+//
+// Windowed schedule over a flattened stream: per key polynomial l the steps
+// run y = 0 .. P - 1 (P = NB + MR - 1); step y loads s_l(y - MR + 1) of limb
+// t (s(x) = diagonal tile mb0 - x) and the digit tiles of K-block
+// y - MR + 1, and for y >= MR - 1, i.e. K-block kb = y - MR + 1 >= 0, row
+// tile r multiplies s(kb - r), loaded r steps earlier, by the digit tiles
+// of K-block kb.  The first MR - 1 steps of every l only fill the window,
+// so the load pipeline runs on through the l boundaries.  Rings: key tiles
+// in RA = 2 MR slots (window MR, prefetch MR), digit tiles in RB = 4 slots
+// (prefetch 3), s(X) and beta(X) in slot X mod RA / RB, the loop unrolled
+// max(RA, RB) times so that every slot index is a compile-time constant.
+template <int MR, int NC, class Init>
+__device__ __forceinline__ void limb_gemm(const Operands &o, int t, int lane, v16i (&acc)[MR][NC],
+                                          Init init) {
+    constexpr int RA = 2 * MR, DA = MR, RB = 4, U = RA > RB ? RA : RB;
+    static_assert(U % RA == 0 && U % RB == 0, "ring sizes must divide the unroll");
+    const Streams S(o, MR, lane, MR - 1);
+    const int P = S.P, steps = o.ell * P, W = MR - 1;
+    v4i win[RA], sb[RB][NC];
+    Cursor qa = S.at(0), qb = S.at(0);
+    // alpha(0..DA-1) and beta(0..RB-2), interleaved as the loop issues them
+#pragma unroll
+    for (int x = 0; x < (DA > RB - 1 ? DA : RB - 1); ++x) {
+        if (x < DA) {
+            win[x] = S.key(qa, t);
+            S.next(qa);
+        }
+        if (x < RB - 1) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) sb[x][c] = S.digits(qb, c);
+            S.next(qb);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    init();  // may load and set acc, once the prologue's loads are in flight
+    int ys = 0;  // y of the current step
+    // Step X first refills the slots step X-1 freed, alpha(X + DA) over
+    // alpha(X - MR) and beta(X + RB - 1) over beta(X - 1), then multiplies.
+    auto step = [&](int u) {  // u = X mod U
+        win[(u + DA) % RA] = S.key(qa, t);
+        S.next(qa);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) sb[(u + RB - 1) % RB][c] = S.digits(qb, c);
+        S.next(qb);
+        if (ys >= W) {
+#pragma unroll
+            for (int r = 0; r < MR; ++r)
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+                    acc[r][c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(win[(u - r + RA) % RA], sb[u % RB][c],
+                                                                      acc[r][c], 0, 0, 0);
+        }
+        ys = ys + 1 == P ? 0 : ys + 1;
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    int X = 0;
+    for (; X + U <= steps; X += U) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) step(u);
+    }
+#pragma unroll
+    for (int u = 0; u < U - 1; ++u)
+        if (X + u < steps) step(u);
+}
+
+// Workgroup task of the limb-split GEMMs: (unit, row block, NC gate tiles),
+// the gate group fastest (spread over the XCDs).
+template <int NC>
+__device__ __forceinline__ Task decode_limb_task(int GT, int RB) {
+    const int GG = (GT + NC - 1) / NC;
+    int task = blockIdx.x;
+    Task t;
+    const int gg = task % GG;
+    task /= GG;
+    t.rb = task % RB;
+    t.unit = task / RB;
+    t.gt0 = gg * NC;
+    t.nc_valid = GT - t.gt0 < NC ? GT - t.gt0 : NC;
+    return t;
+}
+
+// Read-modify-write seed: the old output tiles start wave 0's accumulators
+// (low 24 bits) and wave 3's (high 8 bits), which keeps every limb sum
+// inside int32 and makes the combined sum old + product.  Loaded after the
+// contraction's first loads are issued, so both latencies overlap.
+template <int MR, int NC>
+__device__ __forceinline__ void load_old(const uint32_t *base, size_t gate_stride, const Task &tk,
+                                         int lane, v16i (&acc)[MR][NC]) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int r = 0; r < MR; ++r) {
+            const uint32_t *row = tile_row<MR>(const_cast<uint32_t *>(base), gate_stride, tk,
+                                               c < tk.nc_valid ? c : 0, r, lane);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint4 v = *reinterpret_cast<const uint4 *>(row + 8 * q);
+                acc[r][c][4 * q + 0] = (int)v.x;
+                acc[r][c][4 * q + 1] = (int)v.y;
+                acc[r][c][4 * q + 2] = (int)v.z;
+                acc[r][c][4 * q + 3] = (int)v.w;
+            }
+        }
+}
+template <int MR, int NC>
+__device__ __forceinline__ void seed_old(int t, v16i (&acc)[MR][NC]) {
+#pragma unroll
+    for (int r = 0; r < MR; ++r)
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+                acc[r][c][e] = t == 0 ? (int)((uint32_t)acc[r][c][e] & 0xFFFFFFu)
+                                      : (int)((uint32_t)acc[r][c][e] >> 24);
+}
+
+// Combines the four waves' limb sums and stores the valid gate tiles.  Tile
+// i = (r, c) passes through LDS buffer i % 2 ([4 limbs][4 quads][64 lanes]
+// of uint4): wave t writes its registers shifted by 8t, and after the
+// barrier sums the four limbs of quad t, i.e. words 8t..8t+3 of its lane's
+// rows, and stores them.  The second buffer lets tile i+1 be written while
+// tile i is still being read; tile i+2 reuses buffer i % 2 only after the
+// barrier of tile i+1, which every wave passes after its reads of tile i.
+template <int MR, int NC>
+__device__ __forceinline__ void combine_store(uint32_t *base, size_t gate_stride, const Task &tk, int t,
+                                              int lane, const v16i (&acc)[MR][NC], uint4 *red) {
+#pragma unroll
+    for (int i = 0; i < MR * NC; ++i) {
+        const int r = i / NC, c = i % NC;
+        uint4 *buf = red + (i & 1) * 4 * 4 * 64;
+        const uint32_t sh = 8u * (uint32_t)t;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            buf[(t * 4 + q) * 64 + lane] =
+                make_uint4((uint32_t)acc[r][c][4 * q + 0] << sh, (uint32_t)acc[r][c][4 * q + 1] << sh,
+                           (uint32_t)acc[r][c][4 * q + 2] << sh, (uint32_t)acc[r][c][4 * q + 3] << sh);
+        __syncthreads();
+        uint4 sum = buf[t * 64 + lane];
+#pragma unroll
+        for (int s = 1; s < 4; ++s) {
+            const uint4 v = buf[(s * 4 + t) * 64 + lane];
+            sum.x += v.x;
+            sum.y += v.y;
+            sum.z += v.z;
+            sum.w += v.w;
+        }
+        if (c < tk.nc_valid) *reinterpret_cast<uint4 *>(tile_row<MR>(base, gate_stride, tk, c, r, lane) + 8 * t) = sum;
+    }
+}
+
+// Stage 1, limb-split (units as in mfma_gemm1_kernel).
+template <int MR, int NC, int OCC>
+__global__ __launch_bounds__(256, OCC) void mfma_gemm1_limb_kernel(MfmaArgs a, int party, int bit, int live) {
+    __shared__ __align__(16) uint4 red[2 * 4 * 4 * 64];
+    const int N = a.N, NB = N / 32, ND = 2 * NB - 1, K1 = a.k + 1, ell = a.ell;
+    const int GT = a.GP / 32;
+    const Task tk = decode_limb_task<NC>(GT, NB / MR);
+    const int lane = threadIdx.x & 63;
+    const int t = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
+    const int kind = tk.unit / live, j = tk.unit % live;
+    const size_t poly_tiles = (size_t)4 * ND * kTileBytes;
+    Operands o;
+    o.A = kind == 0 ? a.bk + (((size_t)party * a.n + bit) * 3 + 0) * ell * poly_tiles
+                    : a.evk + (size_t)j * ell * poly_tiles;
+    o.B = a.U + ((size_t)j * ell * GT + tk.gt0) * NB * kTileBytes;
+    o.b_poly = (uint32_t)((size_t)GT * NB * kTileBytes);
+    o.ell = ell; o.NB = NB; o.mb0 = tk.rb * MR; o.nc_valid = tk.nc_valid;
+    uint32_t *base = kind == 0 ? a.acc + (size_t)j * N : a.W + (size_t)j * a.GP * N;
+    const size_t gate_stride = kind == 0 ? (size_t)K1 * N : (size_t)N;
+    v16i acc[MR][NC];
+#pragma unroll
+    for (int r = 0; r < MR; ++r)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[r][c] = v16i{};
+    const bool seed = kind == 0 && (t == 0 || t == 3);  // c'_j is added to ACC_j
+    limb_gemm<MR, NC>(o, t, lane, acc, [&]() {
+        if (seed) {
+            load_old<MR, NC>(base, gate_stride, tk, lane, acc);
+            seed_old<MR, NC>(t, acc);
+        }
+    });
+    combine_store<MR, NC>(base, gate_stride, tk, t, lane, acc, red);
+}
+
+// Stage 2, limb-split: unit o adds sum_l T(f_o,l) V_l to ACC_{o ? 1+party : 0}.
+template <int MR, int NC, int OCC>
+__global__ __launch_bounds__(256, OCC) void mfma_gemm2_limb_kernel(MfmaArgs a, int party, int bit) {
+    __shared__ __align__(16) uint4 red[2 * 4 * 4 * 64];
+    const int N = a.N, NB = N / 32, ND = 2 * NB - 1, K1 = a.k + 1, ell = a.ell;
+    const int GT = a.GP / 32;
+    const Task tk = decode_limb_task<NC>(GT, NB / MR);
+    const int lane = threadIdx.x & 63;
+    const int t = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
+    const size_t poly_tiles = (size_t)4 * ND * kTileBytes;
+    Operands o;
+    o.A = a.bk + ((((size_t)party * a.n + bit) * 3 + 1 + tk.unit) * ell) * poly_tiles;
+    o.B = a.V + (size_t)tk.gt0 * NB * kTileBytes;
+    o.b_poly = (uint32_t)((size_t)GT * NB * kTileBytes);
+    o.ell = ell; o.NB = NB; o.mb0 = tk.rb * MR; o.nc_valid = tk.nc_valid;
+    uint32_t *base = a.acc + (size_t)(tk.unit == 0 ? 0 : 1 + party) * N;
+    v16i acc[MR][NC];
+#pragma unroll
+    for (int r = 0; r < MR; ++r)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[r][c] = v16i{};
+    const bool seed = t == 0 || t == 3;
+    limb_gemm<MR, NC>(o, t, lane, acc, [&]() {
+        if (seed) {
+            load_old<MR, NC>(base, (size_t)K1 * N, tk, lane, acc);
+            seed_old<MR, NC>(t, acc);
+        }
+    });
+    combine_store<MR, NC>(base, (size_t)K1 * N, tk, t, lane, acc, red);
+}
+
+// Tile configurations of the two GEMMs.  Limb-split shapes (LIMB): MR row
+// tiles x NC gate tiles per workgroup, one limb per wave; shared-key shape:
+// MR row tiles x NC gate tiles per wave, four limbs per wave, four gate
+// tiles per workgroup.  OCC: workgroups per CU the register budget is sized
+// for.  The autotuner picks one per batch shape.
 struct GemmShape {
     int MR, NC;
 };
-constexpr GemmShape kShapes[] = {{2, 1}, {4, 1}, {2, 2}, {2, 1}, {4, 1}};
+constexpr GemmShape kShapes[] = {{8, 1}, {4, 2}, {4, 1}, {2, 1}, {8, 2}};
 constexpr int kNumShapes = 5;
 
-// Shapes 3 and 4 share each K-block's key tiles through LDS.
 template <int V>
 struct ShapeOf;
-template <> struct ShapeOf<0> { static constexpr int MR = 2, NC = 1, OCC = 2; static constexpr bool SH = false; };
-template <> struct ShapeOf<1> { static constexpr int MR = 4, NC = 1, OCC = 1; static constexpr bool SH = false; };
-template <> struct ShapeOf<2> { static constexpr int MR = 2, NC = 2, OCC = 1; static constexpr bool SH = false; };
-template <> struct ShapeOf<3> { static constexpr int MR = 2, NC = 1, OCC = 2; static constexpr bool SH = true; };
-template <> struct ShapeOf<4> { static constexpr int MR = 4, NC = 1, OCC = 1; static constexpr bool SH = true; };
+template <> struct ShapeOf<0> { static constexpr int MR = 8, NC = 1, OCC = 2; static constexpr bool LIMB = true; };
+template <> struct ShapeOf<1> { static constexpr int MR = 4, NC = 2, OCC = 2; static constexpr bool LIMB = true; };
+template <> struct ShapeOf<2> { static constexpr int MR = 4, NC = 1, OCC = 3; static constexpr bool LIMB = true; };
+template <> struct ShapeOf<3> { static constexpr int MR = 2, NC = 1, OCC = 2; static constexpr bool LIMB = false; };
+template <> struct ShapeOf<4> { static constexpr int MR = 8, NC = 2, OCC = 1; static constexpr bool LIMB = true; };
 
 template <int V>
 static void launch_g1(const MfmaArgs &a, int party, int bit, int live, int GT, int NB, hipStream_t s) {
     using S = ShapeOf<V>;
-    const int GG = (GT + kWaves * S::NC - 1) / (kWaves * S::NC);
-    const unsigned g = (unsigned)(2 * live * (NB / S::MR) * GG);
-    hipLaunchKernelGGL((mfma_gemm1_kernel<S::MR, S::NC, S::OCC, S::SH>), dim3(g), dim3(64 * kWaves), 0, s,
-                       a, party, bit, live);
+    if constexpr (S::LIMB) {
+        const unsigned g = (unsigned)(2 * live * (NB / S::MR) * ((GT + S::NC - 1) / S::NC));
+        hipLaunchKernelGGL((mfma_gemm1_limb_kernel<S::MR, S::NC, S::OCC>), dim3(g), dim3(256), 0, s, a, party,
+                           bit, live);
+    } else {
+        const int GG = (GT + kWaves * S::NC - 1) / (kWaves * S::NC);
+        const unsigned g = (unsigned)(2 * live * (NB / S::MR) * GG);
+        hipLaunchKernelGGL((mfma_gemm1_kernel<S::MR, S::NC, S::OCC>), dim3(g), dim3(64 * kWaves), 0, s,
+                           a, party, bit, live);
+    }
 }
 template <int V>
 static void launch_g2(const MfmaArgs &a, int party, int bit, int GT, int NB, hipStream_t s) {
     using S = ShapeOf<V>;
-    const int GG = (GT + kWaves * S::NC - 1) / (kWaves * S::NC);
-    const unsigned g = (unsigned)(2 * (NB / S::MR) * GG);
-    hipLaunchKernelGGL((mfma_gemm2_kernel<S::MR, S::NC, S::OCC, S::SH>), dim3(g), dim3(64 * kWaves), 0, s,
-                       a, party, bit);
+    if constexpr (S::LIMB) {
+        const unsigned g = (unsigned)(2 * (NB / S::MR) * ((GT + S::NC - 1) / S::NC));
+        hipLaunchKernelGGL((mfma_gemm2_limb_kernel<S::MR, S::NC, S::OCC>), dim3(g), dim3(256), 0, s, a, party,
+                           bit);
+    } else {
+        const int GG = (GT + kWaves * S::NC - 1) / (kWaves * S::NC);
+        const unsigned g = (unsigned)(2 * (NB / S::MR) * GG);
+        hipLaunchKernelGGL((mfma_gemm2_kernel<S::MR, S::NC, S::OCC>), dim3(g), dim3(64 * kWaves), 0, s,
+                           a, party, bit);
+    }
 }
 static void gemm1(int v, const MfmaArgs &a, int party, int bit, int live, int GT, int NB, hipStream_t s) {
     switch (v) {
@@ -595,6 +872,9 @@ static int prepare(mk_ctx *ctx, const uint32_t *abar, size_t count, hipStream_t 
     const int K1 = P.k + 1, N = P.N, ell = P.bk_ell;
     const size_t acc_b = GP * K1 * N * 4, w_b = (size_t)K1 * GP * N * 4;
     const size_t u_b = (size_t)K1 * ell * GP * N, v_b = (size_t)ell * GP * N;
+    // the GEMMs address a key polynomial's digit block with 32-bit offsets
+    if (u_b >= ((size_t)1 << 31))
+        return fail(MK_EINVAL, "int8-MFMA path: batch too large for one launch (split it)");
     DeviceKeys &D = ctx->dev;
     const size_t need = acc_b + w_b + u_b + v_b;
     if (D.mfma_scratch_bytes < need) {
@@ -624,11 +904,18 @@ static int prepare(mk_ctx *ctx, const uint32_t *abar, size_t count, hipStream_t 
     return MK_OK;
 }
 
+// First shape whose row block divides N/32.
+static int default_shape(int NB) {
+    for (int v = 0; v < kNumShapes; ++v)
+        if (NB % kShapes[v].MR == 0) return v;
+    return kNumShapes - 1;
+}
+
 // Tile shapes for a batch of GT gate tiles: forced by mk_set_tiles, else the
-// autotuned choice for this size, else shape 0.
+// autotuned choice for this size, else the default.
 static void shapes_for(const mk_ctx *ctx, int GT, int &v1, int &v2) {
     const DeviceKeys &D = ctx->dev;
-    v1 = v2 = 0;
+    v1 = v2 = default_shape(ctx->p.N / 32);
     auto it = D.tuned_tiles.find(GT);
     if (it != D.tuned_tiles.end()) {
         v1 = it->second.first;

@@ -216,6 +216,30 @@ def test_every_tile_shape_is_bit_identical(torch_cuda, shape):
     assert np.array_equal(outs[0], outs[1])
 
 
+def test_smallest_ring_shapes(torch_cuda):
+    """N = 128 (4 K-blocks): the 256-row shapes are refused, the default is
+    the first shape that fits, and every admissible shape matches the
+    oracle, ragged gate tiles included."""
+    K, ctx = helpers.gpu_world("C1S")
+    assert ctx.get_tiles(100) == (1, 1)
+    for bad in (0, 4):
+        with pytest.raises(Exception):
+            ctx.set_tiles(bad, bad)
+    types, m1, m2 = mi.gate_batch(45, seed=14)
+    c1, c2 = _workload(K, types, m1, m2, seed=140)
+    ref = helpers.oracle_gates("C1S", types, c1, c2)
+    for shape in (1, 2, 3):
+        ctx.set_tiles(shape, shape)
+        try:
+            got = _gates_on_gpu(torch_cuda, ctx, types, c1, c2, 1)
+        finally:
+            ctx.set_tiles(-1, -1)
+        assert np.array_equal(got, ref), shape
+    v1, v2, ms = ctx.autotune(45)
+    assert v1 in (1, 2, 3) and v2 in (1, 2, 3)
+    assert ms[0] == 0 and ms[4] == 0 and ms[5] == 0 and ms[9] == 0
+
+
 def test_autotune_picks_valid_shapes(torch_cuda):
     K, ctx = helpers.gpu_world("C1")
     v1, v2, ms = ctx.autotune(300)

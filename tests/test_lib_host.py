@@ -113,6 +113,12 @@ def test_tile_shape_arguments():
     assert ctx.get_tiles(1000) == (0, 0)
     with pytest.raises(mk.MkError):
         ctx.set_tiles(5, 0)
+    small = mk.Context(helpers.lib_params(OP.C1S), 3)   # N/32 = 4: 256-row shapes refused
+    assert small.get_tiles(1000) == (1, 1)
+    with pytest.raises(mk.MkError):
+        small.set_tiles(0, 1)
+    with pytest.raises(mk.MkError):
+        small.set_tiles(1, 4)
     with pytest.raises(mk.MkError) as e:      # needs the uploaded key
         ctx.autotune(64, stream=0)
     assert e.value.code == -4
