@@ -198,12 +198,15 @@ int mk_circuit_stats(const mk_circuit *c, int32_t *n_levels, int64_t *live_gates
  *     (k+1)*N words (the RLWE accumulator c_0..c_k) after the first
  *     `max_steps` CMux steps (all k*n when max_steps < 0).
  *   mk_extract_keyswitch: acc_dev rows of (k+1)*N words -> out_dev LWE rows
- *     (sample extraction, + 1/8, key switching). */
+ *     (sample extraction, + 1/8, key switching); MK_PATH_I32 sums the
+ *     selected key-switching rows with 32-bit adds, MK_PATH_MFMA_I8 runs the
+ *     same sums as a one-hot int8-MFMA GEMM per party (kept on 32-bit adds
+ *     when a party's tile set would exceed 2 GiB).  Both are exact. */
 int mk_blind_rotate(mk_ctx *ctx, const uint32_t *abar_dev, uint32_t *acc_dev,
                     size_t count, int max_steps, int path, void *stream);
 int mk_extract_keyswitch(mk_ctx *ctx, const uint32_t *acc_dev,
                          uint32_t *out_dev, size_t count, size_t stride,
-                         void *stream);
+                         int path, void *stream);
 
 /* Netlist builders (§4.3-§4.5).  Each writes into caller-provided arrays
  * sized by a first call with gates == NULL (which only sets *n_gates and

@@ -62,6 +62,11 @@ TOY = Params(k=2, n=16, N=64, bk_ell=3, ks_t=8,
              bk_noise_log2=30, ks_noise_log2=24, lwe_noise_log2=20)
 
 
+# Toy shape with base-8 key switching (3-bit digits), 3 parties.
+TOYB3 = Params(k=3, n=16, N=64, bk_ell=3, ks_t=5,
+               bk_noise_log2=30, ks_noise_log2=24, lwe_noise_log2=20, ks_log_base=3)
+
+
 def toy(k: int) -> Params:
     return Params(k=k, n=16, N=64, bk_ell=3, ks_t=8,
                   bk_noise_log2=30, ks_noise_log2=24, lwe_noise_log2=20)

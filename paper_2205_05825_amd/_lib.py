@@ -62,7 +62,7 @@ _SIGS = {
     "mk_bootstrap_gate": ([_vp, _vp, _vp, _vp, _vp, _sz, _sz, _i, _vp], _i),
     "mk_eval_circuit": ([_vp, ctypes.POINTER(MkCircuit), _vp, _vp, _sz, _sz, _i, _vp], _i),
     "mk_blind_rotate": ([_vp, _vp, _vp, _sz, _i, _i, _vp], _i),
-    "mk_extract_keyswitch": ([_vp, _vp, _vp, _sz, _sz, _vp], _i),
+    "mk_extract_keyswitch": ([_vp, _vp, _vp, _sz, _sz, _i, _vp], _i),
     "mk_build_operator": ([_i, _i, ctypes.POINTER(MkGate), ctypes.POINTER(ctypes.c_int32),
                            ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                            ctypes.POINTER(ctypes.c_int32)], _i),
@@ -244,9 +244,9 @@ class Context:
         _check(_L.mk_blind_rotate(self._h, _ptr(abar), _ptr(acc), abar.shape[0], max_steps,
                                   path, _stream(stream)))
 
-    def extract_keyswitch(self, acc, out, stream=None):
+    def extract_keyswitch(self, acc, out, path=PATH_MFMA_I8, stream=None):
         _check(_L.mk_extract_keyswitch(self._h, _ptr(acc), _ptr(out), acc.shape[0],
-                                       out.shape[1], _stream(stream)))
+                                       out.shape[1], path, _stream(stream)))
 
     def eval_circuit(self, circuit: "Circuit", inp, out, path=PATH_MFMA_I8, stream=None):
         batch = inp.shape[1]

@@ -98,8 +98,8 @@ static int check_uploaded(const mk_ctx *ctx) {
 void device_release(mk_ctx *ctx) {
     drain_events(ctx);
     DeviceKeys &D = ctx->dev;
-    void *ptrs[] = {D.bk_ext, D.evk_ext, D.bk_win, D.evk_win, D.ks, D.scratch, D.mfma_scratch,
-                    D.circ_scratch};
+    void *ptrs[] = {D.bk_ext, D.evk_ext, D.bk_win, D.evk_win, D.ks, D.ks_win, D.scratch, D.mfma_scratch,
+                    D.ks_scratch, D.circ_scratch};
     bool any = false;
     for (void *p : ptrs) any |= p != nullptr;
     if (any) {
@@ -166,6 +166,7 @@ int device_upload(mk_ctx *ctx, void *stream) {
     if ((rc = dev_alloc_copy(&D.evk_ext, evk_ext, s, "evk_ext"))) return rc;
     if ((rc = dev_alloc_copy(&D.ks, ks, s, "ks"))) return rc;
     if ((rc = mfma_upload(ctx, evk, s))) return rc;
+    if ((rc = ks_mfma_upload(ctx, s))) return rc;
     MK_HIP(hipStreamSynchronize(s), "upload sync");
     D.uploaded = true;
     return MK_OK;
@@ -478,6 +479,15 @@ int run_blind_rotate(mk_ctx *ctx, const uint32_t *abar, uint32_t *acc, size_t co
     return fail(MK_EINVAL, "unknown path");
 }
 
+int run_key_switch(mk_ctx *ctx, const uint32_t *acc, uint32_t *out, size_t count, size_t stride, int path,
+                   hipStream_t s) {
+    if (path == MK_PATH_I32) return launch_extract_ks(ctx, acc, out, count, stride, s);
+    if (path == MK_PATH_MFMA_I8)
+        return ctx->dev.ks_win ? launch_ks_mfma(ctx, acc, out, count, stride, s)
+                               : launch_extract_ks(ctx, acc, out, count, stride, s);
+    return fail(MK_EINVAL, "unknown path");
+}
+
 int run_gates(mk_ctx *ctx, const uint8_t *types, const uint32_t *in1, const uint32_t *in2,
               uint32_t *out, size_t count, size_t stride, int path, hipStream_t s) {
     const mk_params &P = ctx->p;
@@ -497,7 +507,7 @@ int run_gates(mk_ctx *ctx, const uint8_t *types, const uint32_t *in1, const uint
     }
     MK_HIP(hipGetLastError(), "precombine launch");
     if ((rc = run_blind_rotate(ctx, abar, acc, count, P.k * P.n, path, s))) return rc;
-    return launch_extract_ks(ctx, acc, out, count, stride, s);
+    return run_key_switch(ctx, acc, out, count, stride, path, s);
 }
 
 }  // namespace mk
@@ -569,13 +579,13 @@ int mk_blind_rotate(mk_ctx *ctx, const uint32_t *abar_dev, uint32_t *acc_dev, si
 }
 
 int mk_extract_keyswitch(mk_ctx *ctx, const uint32_t *acc_dev, uint32_t *out_dev, size_t count,
-                         size_t stride, void *stream) {
+                         size_t stride, int path, void *stream) {
     if (!ctx || (count && (!acc_dev || !out_dev))) return fail(MK_EINVAL, "mk_extract_keyswitch: null argument");
     if (stride < lwe_words(ctx->p)) return fail(MK_EINVAL, "mk_extract_keyswitch: stride < kn+1");
     int rc = check_uploaded(ctx);
     if (rc) return rc;
     if (!count) return MK_OK;
-    return launch_extract_ks(ctx, acc_dev, out_dev, count, stride, (hipStream_t)stream);
+    return run_key_switch(ctx, acc_dev, out_dev, count, stride, path, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -25,8 +25,6 @@ namespace mk {
 
 int run_blind_rotate(mk_ctx *ctx, const uint32_t *abar, uint32_t *acc, size_t count, int steps,
                      int path, hipStream_t s);
-int launch_extract_ks(mk_ctx *ctx, const uint32_t *acc, uint32_t *out, size_t count, size_t stride,
-                      hipStream_t s);
 
 namespace {
 
@@ -391,8 +389,8 @@ int mk_eval_circuit(mk_ctx *ctx, const mk_circuit *c, const uint32_t *in_dev, ui
         }
         if (hipGetLastError() != hipSuccess) return bail(MK_EDEVICE, "circuit precombine launch failed");
         if ((rc = run_blind_rotate(ctx, abar, acc, count, Pm.k * Pm.n, path, s)) ||
-            (rc = launch_extract_ks(ctx, acc, wires + (size_t)P.level_base[l] * batch * stride, count,
-                                    stride, s))) {
+            (rc = run_key_switch(ctx, acc, wires + (size_t)P.level_base[l] * batch * stride, count, stride,
+                                 path, s))) {
             (void)hipStreamSynchronize(s);
             return rc;
         }

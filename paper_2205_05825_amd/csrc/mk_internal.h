@@ -39,6 +39,8 @@ struct DeviceKeys {
     int8_t *evk_win = nullptr;
     size_t bk_win_bytes = 0, evk_win_bytes = 0;
     uint32_t *ks = nullptr;       // [k][N][t][B'-1][n+1]
+    int8_t *ks_win = nullptr;     // MFMA key-switching tiles (mk_keyswitch.hip)
+    size_t ks_win_bytes = 0;
     // Profiling: event pairs per stage, accumulated on mk_get_profile.
     int profiling = 0;
     std::vector<std::pair<void *, void *>> events[MK_PROFILE_SLOTS];
@@ -49,6 +51,8 @@ struct DeviceKeys {
     size_t scratch_bytes = 0;
     void *mfma_scratch = nullptr;
     size_t mfma_scratch_bytes = 0;
+    void *ks_scratch = nullptr;     // rounded coefficients of the MFMA key switch
+    size_t ks_scratch_bytes = 0;
     void *circ_scratch = nullptr;   // circuit wire buffer and descriptors
     size_t circ_scratch_bytes = 0;
     // GEMM tile shapes of the MFMA rotation: autotuned per batch size (in

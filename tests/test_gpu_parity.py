@@ -106,25 +106,39 @@ def test_blind_rotate_partial_c2(torch_cuda, path):
         assert np.array_equal(got[g], refs[g]), g
 
 
-def test_extract_keyswitch_stage_c2(torch_cuda):
-    K, ctx = helpers.gpu_world("C2")
+def _keyswitch_case(torch_cuda, name, cnt, path, seed):
+    K, ctx = helpers.gpu_world(name)
     P = K.params
-    rng = np.random.default_rng(5)
-    cnt = 6
+    rng = np.random.default_rng(seed)
     acc = rng.integers(0, 1 << 32, (cnt, (P.k + 1) * P.N), dtype=np.uint64).astype(np.uint32)
     acc[1] = 0
+    acc[2, :] = 0xFFFFFFFF       # every digit at its maximum after rounding
     d = torch_cuda.device("cuda:0")
     tacc = torch_cuda.from_numpy(acc.view(np.int32)).to(d)
     stride = P.lwe_words + 3
     out = torch_cuda.full((cnt, stride), 7, dtype=torch_cuda.int32, device=d)
-    ctx.extract_keyswitch(tacc, out)
+    ctx.extract_keyswitch(tacc, out, path=path)
     torch_cuda.cuda.synchronize()
     got = out.cpu().numpy().view(np.uint32)
     for g in range(cnt):
         big = tfhe.sample_extract(acc[g].reshape(P.k + 1, P.N))
         big[0] = np.uint32((int(big[0]) + tfhe.EIGHTH) & 0xFFFFFFFF)
-        assert np.array_equal(got[g, :P.lwe_words], tfhe.key_switch(K, big)), g
+        assert np.array_equal(got[g, :P.lwe_words], tfhe.key_switch(K, big)), (name, g)
         assert (got[g, P.lwe_words:] == 7).all()      # padding untouched
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_extract_keyswitch_stage_c2(torch_cuda, path):
+    _keyswitch_case(torch_cuda, "C2", 6, path, 5)
+
+
+@pytest.mark.parametrize("name,cnt", [("C1", 70), ("C1B4", 33), ("TOYB3", 41)])
+def test_extract_keyswitch_shapes(torch_cuda, name, cnt):
+    """Key switching on both paths: t = 6 digits (padded one-hot blocks),
+    k = 4 parties (column 0 summed over parties), base-8 digits (generic
+    one-hot, two K-blocks per coefficient), ragged gate tiles."""
+    for path in PATHS:
+        _keyswitch_case(torch_cuda, name, cnt, path, 50 + cnt)
 
 
 @pytest.mark.parametrize("path", PATHS)
