@@ -275,23 +275,28 @@ struct Operands {
     int ell, NB, mb0, nc_valid;
 };
 
-// Position in the flattened step stream: (l, y) and the byte offsets of
-// limb 0 of alpha and of gate tile 0 of beta there.  Advancing is
-// branch-free (masks, not conditionals), so the compiler keeps every load of
-// the unrolled loop in one basic block and its load counters exact.
+// Position in the flattened step stream: the byte offsets of limb 0 of
+// alpha and of gate tile 0 of beta there, and rem = P - y, the steps left
+// in the current key polynomial.  Advancing is branch-free and costs a few
+// scalar instructions (the wrap to the next l is one select), so the
+// compiler keeps every load of the unrolled loop in one basic block and its
+// load counters exact.  Past the last polynomial both offsets run beyond
+// their descriptors' ranges and the loads return zeros.
 struct Cursor {
-    int l, y;
     uint32_t a, b;
+    int rem;
 };
 
 // Digit K-block of step y is y - dshift (0 for the skewed schedule, MR - 1
-// for the windowed one); K-blocks outside [0, NB) read as zero.
+// for the windowed one).  Only the skewed schedule multiplies digit tiles
+// outside [0, NB), which must read as zero (zero_edges).
 struct Streams {
     __amdgpu_buffer_rsrc_t ra, rb;
-    int ell, NB, ND, P, MRm1, nc_valid, dshift;
+    int NB, ND, P, MRm1, dshift, nc_valid;
     uint32_t lane16, a_wrap, b_wrap, limb_stride, tile_stride, b_poly, mb0;
     __device__ __forceinline__ Streams(const Operands &o, int MR, int lane, int dshift_) {
-        ell = o.ell; NB = o.NB; ND = 2 * NB - 1; P = NB + MR - 1; MRm1 = MR - 1; dshift = dshift_;
+        const int ell = o.ell;
+        NB = o.NB; ND = 2 * NB - 1; P = NB + MR - 1; MRm1 = MR - 1; dshift = dshift_;
         nc_valid = o.nc_valid; lane16 = (uint32_t)lane * 16; b_poly = o.b_poly; mb0 = (uint32_t)o.mb0;
         limb_stride = (uint32_t)ND * kTileBytes;
         tile_stride = (uint32_t)NB * kTileBytes;
@@ -304,35 +309,37 @@ struct Streams {
                                                (int)((ell - 1) * b_poly + nv * NB * kTileBytes), kBufWord3);
     }
     __device__ __forceinline__ Cursor at(int X) const {  // setup only (divides)
+        const int l = X / P, y = X - l * P;
         Cursor q;
-        q.l = X / P;
-        q.y = X - q.l * P;
-        q.a = (uint32_t)((4 * q.l * ND + (int)mb0 - (q.y - MRm1) + NB - 1) * kTileBytes);
-        q.b = (uint32_t)q.l * b_poly + (uint32_t)((q.y - dshift) * kTileBytes);
+        q.a = (uint32_t)((4 * l * ND + (int)mb0 - (y - MRm1) + NB - 1) * kTileBytes);
+        q.b = (uint32_t)l * b_poly + (uint32_t)((y - dshift) * kTileBytes);
+        q.rem = P - y;
         return q;
     }
     __device__ __forceinline__ void next(Cursor &q) const {
-        q.y += 1;
         q.a -= kTileBytes;
         q.b += kTileBytes;
-        const uint32_t w = 0u - (uint32_t)(q.y == P);  // all ones at a wrap
-        q.y &= ~(int)w;
-        q.l += (int)(w & 1u);
-        q.a += a_wrap & w;
-        q.b += b_wrap & w;
+        const bool wrap = --q.rem == 0;
+        q.a += wrap ? a_wrap : 0u;
+        q.b += wrap ? b_wrap : 0u;
+        q.rem += wrap ? P : 0;
     }
-    // limb t of alpha at q (zero past the last polynomial); the selects are
-    // on uniform values (scalar), the lane offset is added last
-    __device__ __forceinline__ v4i key(const Cursor &q, int t) const {
-        const uint32_t uni = q.l < ell ? q.a + t * limb_stride : kOutOfRange;
-        return (v4i)__builtin_amdgcn_raw_buffer_load_b128(ra, uni + lane16, 0, 0);
+    // per-wave vector offsets: limb t of alpha, gate tile c of beta (gate
+    // tiles beyond the batch read zeros)
+    __device__ __forceinline__ uint32_t key_lane(int t) const { return t * limb_stride + lane16; }
+    __device__ __forceinline__ uint32_t dig_lane(int c) const {
+        return c < nc_valid ? c * tile_stride + lane16 : kOutOfRange + lane16;
     }
-    // gate tile c of beta at q (zero outside the K-blocks, past the last
-    // polynomial and for gate tiles beyond the batch)
-    __device__ __forceinline__ v4i digits(const Cursor &q, int c) const {
-        const bool valid = (unsigned)(q.y - dshift) < (unsigned)NB && q.l < ell && c < nc_valid;
-        const uint32_t uni = valid ? q.b + c * tile_stride : kOutOfRange;
-        return (v4i)__builtin_amdgcn_raw_buffer_load_b128(rb, uni + lane16, 0, 0);
+    __device__ __forceinline__ v4i key(const Cursor &q, uint32_t vlane) const {
+        return (v4i)__builtin_amdgcn_raw_buffer_load_b128(ra, q.a + vlane, 0, 0);
+    }
+    // digit K-block y - dshift; with zero_edges, K-blocks outside [0, NB)
+    // (y >= NB for the skewed schedule) read as zero
+    template <bool zero_edges>
+    __device__ __forceinline__ v4i digits(const Cursor &q, uint32_t vlane) const {
+        uint32_t uni = q.b;
+        if constexpr (zero_edges) uni |= q.rem > P - NB ? 0u : kOutOfRange;
+        return (v4i)__builtin_amdgcn_raw_buffer_load_b128(rb, uni + vlane, 0, 0);
     }
 };
 
@@ -347,6 +354,11 @@ __device__ __forceinline__ void toeplitz_gemm(const Operands &o, int lane, v16i 
     constexpr int D = MR > 2 ? MR : 2, R = MR + D;
     const Streams S(o, MR, lane, 0);
     const int steps = o.ell * S.P;
+    uint32_t vk[4], vd[NC];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) vk[t] = S.key_lane(t);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) vd[c] = S.dig_lane(c);
     v4i sa[R][4], sb[R][NC];
 #pragma unroll
     for (int i = 1; i < MR; ++i)
@@ -356,9 +368,9 @@ __device__ __forceinline__ void toeplitz_gemm(const Operands &o, int lane, v16i 
 #pragma unroll
     for (int x = 0; x <= D; ++x) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) sa[x][t] = S.key(q, t);
+        for (int t = 0; t < 4; ++t) sa[x][t] = S.key(q, vk[t]);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) sb[x][c] = S.digits(q, c);
+        for (int c = 0; c < NC; ++c) sb[x][c] = S.digits<true>(q, vd[c]);
         S.next(q);
         __builtin_amdgcn_sched_barrier(0);  // issue in ring order
     }
@@ -373,9 +385,9 @@ __device__ __forceinline__ void toeplitz_gemm(const Operands &o, int lane, v16i 
                     acc[r][c][t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
                         sa[u][t], sb[(u - MR + 1 + r + R) % R][c], acc[r][c][t], 0, 0, 0);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) sa[(u + D + 1) % R][t] = S.key(q, t);
+        for (int t = 0; t < 4; ++t) sa[(u + D + 1) % R][t] = S.key(q, vk[t]);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) sb[(u + D + 1) % R][c] = S.digits(q, c);
+        for (int c = 0; c < NC; ++c) sb[(u + D + 1) % R][c] = S.digits<true>(q, vd[c]);
         S.next(q);
         // keep the scheduler from sinking these loads towards their use
         __builtin_amdgcn_sched_barrier(0);
@@ -592,18 +604,22 @@ __device__ __forceinline__ void limb_gemm(const Operands &o, int t, int lane, v1
     static_assert(U % RA == 0 && U % RB == 0, "ring sizes must divide the unroll");
     const Streams S(o, MR, lane, MR - 1);
     const int P = S.P, steps = o.ell * P, W = MR - 1;
+    const uint32_t vk = S.key_lane(t);
+    uint32_t vd[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) vd[c] = S.dig_lane(c);
     v4i win[RA], sb[RB][NC];
     Cursor qa = S.at(0), qb = S.at(0);
     // alpha(0..DA-1) and beta(0..RB-2), interleaved as the loop issues them
 #pragma unroll
     for (int x = 0; x < (DA > RB - 1 ? DA : RB - 1); ++x) {
         if (x < DA) {
-            win[x] = S.key(qa, t);
+            win[x] = S.key(qa, vk);
             S.next(qa);
         }
         if (x < RB - 1) {
 #pragma unroll
-            for (int c = 0; c < NC; ++c) sb[x][c] = S.digits(qb, c);
+            for (int c = 0; c < NC; ++c) sb[x][c] = S.digits<false>(qb, vd[c]);
             S.next(qb);
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -613,10 +629,10 @@ __device__ __forceinline__ void limb_gemm(const Operands &o, int t, int lane, v1
     // Step X first refills the slots step X-1 freed, alpha(X + DA) over
     // alpha(X - MR) and beta(X + RB - 1) over beta(X - 1), then multiplies.
     auto step = [&](int u) {  // u = X mod U
-        win[(u + DA) % RA] = S.key(qa, t);
+        win[(u + DA) % RA] = S.key(qa, vk);
         S.next(qa);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) sb[(u + RB - 1) % RB][c] = S.digits(qb, c);
+        for (int c = 0; c < NC; ++c) sb[(u + RB - 1) % RB][c] = S.digits<false>(qb, vd[c]);
         S.next(qb);
         if (ys >= W) {
 #pragma unroll
