@@ -184,6 +184,29 @@ int mk_eval_circuit(mk_ctx *ctx, const mk_circuit *c, const uint32_t *in_dev,
                     uint32_t *out_dev, size_t batch, size_t stride, int path,
                     void *stream);
 
+/* An operator's whole level sequence captured as one HIP graph (the
+ * batched, layered evaluation of mk_eval_circuit, replayed without host
+ * work).  mk_circuit_graph_create plans `c` for `batch` instances, takes
+ * the tile shapes tuned for each level's size at that moment, allocates the
+ * graph's own device buffers (wires, descriptors and every scratch buffer
+ * of the path, so later calls on the context cannot move them) and
+ * captures, on a stream of its own, the evaluation reading in_dev and
+ * writing out_dev (layouts as in mk_eval_circuit); in_dev and out_dev must
+ * stay valid for the graph's lifetime.  Each mk_graph_launch on `stream`
+ * then evaluates the circuit on the current contents of in_dev (the
+ * evaluation key must stay uploaded).  Launches of one graph must not
+ * overlap (they share its buffers).  mk_graph_info reports the number of
+ * levels and of bootstrapped gates per launch; mk_graph_destroy waits for
+ * the device and frees everything.  Errors: those of mk_eval_circuit, plus
+ * MK_EDEVICE when capture or instantiation fails. */
+typedef struct mk_graph mk_graph;
+int mk_circuit_graph_create(mk_ctx *ctx, const mk_circuit *c, const uint32_t *in_dev,
+                            uint32_t *out_dev, size_t batch, size_t stride, int path,
+                            mk_graph **graph);
+int mk_graph_launch(mk_graph *graph, void *stream);
+int mk_graph_info(const mk_graph *graph, int32_t *n_levels, int64_t *gates);
+int mk_graph_destroy(mk_graph *graph);
+
 /* Host-side analysis of a netlist as mk_eval_circuit levels it: number of
  * bootstrapping levels, bootstrapped gates actually evaluated, widest level,
  * and wire slots needed per instance.  Any output pointer may be NULL.

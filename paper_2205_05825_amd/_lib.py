@@ -61,6 +61,11 @@ _SIGS = {
     "mk_not": ([_vp, _vp, _vp, _sz, _sz, _vp], _i),
     "mk_bootstrap_gate": ([_vp, _vp, _vp, _vp, _vp, _sz, _sz, _i, _vp], _i),
     "mk_eval_circuit": ([_vp, ctypes.POINTER(MkCircuit), _vp, _vp, _sz, _sz, _i, _vp], _i),
+    "mk_circuit_graph_create": ([_vp, ctypes.POINTER(MkCircuit), _vp, _vp, _sz, _sz, _i,
+                                 ctypes.POINTER(_vp)], _i),
+    "mk_graph_launch": ([_vp, _vp], _i),
+    "mk_graph_info": ([_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)], _i),
+    "mk_graph_destroy": ([_vp], _i),
     "mk_blind_rotate": ([_vp, _vp, _vp, _sz, _i, _i, _vp], _i),
     "mk_extract_keyswitch": ([_vp, _vp, _vp, _sz, _sz, _i, _vp], _i),
     "mk_build_operator": ([_i, _i, ctypes.POINTER(MkGate), ctypes.POINTER(ctypes.c_int32),
@@ -248,10 +253,43 @@ class Context:
         _check(_L.mk_extract_keyswitch(self._h, _ptr(acc), _ptr(out), acc.shape[0],
                                        out.shape[1], path, _stream(stream)))
 
+    def circuit_graph(self, circuit: "Circuit", inp, out, path=PATH_MFMA_I8) -> "Graph":
+        return Graph(self, circuit, inp, out, path)
+
     def eval_circuit(self, circuit: "Circuit", inp, out, path=PATH_MFMA_I8, stream=None):
         batch = inp.shape[1]
         _check(_L.mk_eval_circuit(self._h, ctypes.byref(circuit.c()), _ptr(inp), _ptr(out),
                                   batch, inp.shape[2], path, _stream(stream)))
+
+
+class Graph:
+    """A circuit evaluation captured as a HIP graph on fixed buffers (see
+    mk_circuit_graph_create); launch() replays it on the current inputs."""
+
+    def __init__(self, ctx: "Context", circuit: "Circuit", inp, out, path=PATH_MFMA_I8):
+        self._ctx = ctx                      # keeps the context alive
+        self._bufs = (inp, out)              # the graph reads/writes these
+        self._c = circuit.c()
+        h = ctypes.c_void_p()
+        _check(_L.mk_circuit_graph_create(ctx._h, ctypes.byref(self._c), _ptr(inp), _ptr(out),
+                                          inp.shape[1], inp.shape[2], path, ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(_L.mk_graph_launch(self._h, _stream(stream)))
+
+    def info(self):
+        lv, g = ctypes.c_int32(), ctypes.c_int64()
+        _check(_L.mk_graph_info(self._h, ctypes.byref(lv), ctypes.byref(g)))
+        return lv.value, g.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _L.mk_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
 
 
 @dataclass

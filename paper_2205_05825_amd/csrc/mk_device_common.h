@@ -35,7 +35,9 @@ int ensure_scratch(mk_ctx *ctx, size_t bytes);
 int mfma_upload(mk_ctx *ctx, const std::vector<uint32_t> &evk, hipStream_t s);
 int launch_br_mfma(mk_ctx *ctx, const uint32_t *abar, uint32_t *acc, size_t count, int steps,
                    hipStream_t s);
+size_t mfma_scratch_need(const mk_params &P, size_t count);
 // Key switching as an int8-MFMA GEMM (mk_keyswitch.hip).
+size_t ks_scratch_need(const mk_params &P, size_t count);
 int ks_mfma_upload(mk_ctx *ctx, hipStream_t s);
 int launch_ks_mfma(mk_ctx *ctx, const uint32_t *acc, uint32_t *out, size_t count, size_t stride,
                    hipStream_t s);

@@ -17,9 +17,24 @@
 
 #include <algorithm>
 #include <list>
+#include <new>
+#include <string>
 #include <vector>
 
 #include "mk_device_common.h"
+
+// A captured evaluation of one circuit on fixed buffers; owns its device
+// memory (buf: wires+descriptors, gate scratch, rotation scratch, key-switch
+// scratch) so that later calls on the context cannot move it.
+struct mk_graph {
+    mk_ctx *ctx = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void *buf[4] = {nullptr, nullptr, nullptr, nullptr};
+    size_t bytes[4] = {0, 0, 0, 0};
+    int levels = 0;
+    int64_t gates = 0;
+};
 
 namespace mk {
 
@@ -260,6 +275,8 @@ int plan_circuit(const mk_circuit *c, CircuitPlan &P) {
     return MK_OK;
 }
 
+void graph_release(mk_graph *g);
+
 static int alloc_circ_scratch(mk_ctx *ctx, size_t bytes) {
     DeviceKeys &D = ctx->dev;
     if (D.circ_scratch_bytes >= bytes) return MK_OK;
@@ -275,6 +292,158 @@ static int alloc_circ_scratch(mk_ctx *ctx, size_t bytes) {
     }
     D.circ_scratch_bytes = bytes;
     return MK_OK;
+}
+
+
+// Host side of one circuit evaluation: the plan, the per-level
+// pre-combination descriptors and the device buffer layout.
+struct CircuitRun {
+    CircuitPlan P;
+    std::vector<CircDesc> desc;
+    std::vector<size_t> desc_off;
+    std::vector<OutDesc> od;
+    size_t batch = 0, stride = 0, words = 0;
+    int path = 0, n_inputs = 0, n_outputs = 0;
+    size_t wire_b = 0, desc_b = 0, od_b = 0, abar_b = 0, gate_b = 0;
+    uint32_t *wires = nullptr;
+    CircDesc *d_desc = nullptr;
+    OutDesc *d_od = nullptr;
+};
+
+int build_run(mk_ctx *ctx, const mk_circuit *c, size_t batch, size_t stride, int path, CircuitRun &R,
+              const char *who) {
+    if (!ctx) return fail(MK_EINVAL, std::string(who) + ": null context");
+    if (path != MK_PATH_I32 && path != MK_PATH_MFMA_I8) return fail(MK_EINVAL, std::string(who) + ": bad path");
+    const mk_params &Pm = ctx->p;
+    const size_t words = lwe_words(Pm);
+    if (stride < words) return fail(MK_EINVAL, std::string(who) + ": stride < kn+1");
+    if (!ctx->dev.uploaded) return fail(MK_ESTATE, "evaluation key not uploaded (mk_upload_eval_key)");
+    int rc = plan_circuit(c, R.P);
+    if (rc) return rc;
+    CircuitPlan &P = R.P;
+    R.batch = batch; R.stride = stride; R.words = words; R.path = path;
+    R.n_inputs = c->n_inputs; R.n_outputs = c->n_outputs;
+    const int L = (int)P.levels.size() - 1;
+    R.desc_off.assign(L + 2, 0);
+    for (int l = 1; l <= L; ++l) {
+        R.desc_off[l] = R.desc.size();
+        for (int gi : P.levels[l]) {
+            const mk_gate &g = c->gates[gi];
+            CircDesc d{-1, -1, 0, 0, kGateConst[g.type], 0};
+            const int sc[2] = {kGateS1[g.type], kGateS2[g.type]};
+            const int ins[2] = {g.in1, g.in2};
+            for (int q = 0; q < 2; ++q) {
+                const Ref &r = P.ref[ins[q]];
+                if (r.base < 0) {
+                    d.cst += (uint32_t)(sc[q] * r.cval) * 0x40000000u;
+                } else {
+                    int sv = sc[q];
+                    if (r.neg) {  // s * (1/4 - c)
+                        d.cst += (uint32_t)sv * 0x40000000u;
+                        sv = -sv;
+                    }
+                    (q == 0 ? d.slot1 : d.slot2) = P.slot[r.base];
+                    (q == 0 ? d.s1 : d.s2) = sv;
+                }
+            }
+            R.desc.push_back(d);
+        }
+    }
+    R.desc_off[L + 1] = R.desc.size();
+    R.od.resize(c->n_outputs);
+    for (int i = 0; i < c->n_outputs; ++i) {
+        const Ref &r = P.ref[c->outputs[i]];
+        R.od[i] = r.base < 0 ? OutDesc{-1, 0, (uint32_t)r.cval, 0} : OutDesc{P.slot[r.base], r.neg ? 1 : 0, 0, 0};
+    }
+    R.wire_b = ((size_t)P.total_slots * batch * stride * 4 + 255) / 256 * 256;
+    R.desc_b = (R.desc.size() * sizeof(CircDesc) + 255) / 256 * 256;
+    R.od_b = R.od.size() * sizeof(OutDesc);
+    const size_t maxc = (size_t)P.max_width * batch;
+    R.abar_b = (maxc * words * 4 + 255) / 256 * 256;
+    R.gate_b = R.abar_b + maxc * (Pm.k + 1) * Pm.N * 4;
+    return MK_OK;
+}
+
+// Layout inside one block: wires | descriptors | output descriptors.
+void set_run_buffers(CircuitRun &R, char *base) {
+    R.wires = (uint32_t *)base;
+    R.d_desc = (CircDesc *)(base + R.wire_b);
+    R.d_od = (OutDesc *)(base + R.wire_b + R.desc_b);
+}
+
+int upload_descriptors(const CircuitRun &R, hipStream_t s) {
+    if (!R.desc.empty() && hipMemcpyAsync(R.d_desc, R.desc.data(), R.desc.size() * sizeof(CircDesc),
+                                          hipMemcpyHostToDevice, s) != hipSuccess)
+        return fail(MK_EDEVICE, "circuit descriptor upload failed");
+    if (!R.od.empty() &&
+        hipMemcpyAsync(R.d_od, R.od.data(), R.od_b, hipMemcpyHostToDevice, s) != hipSuccess)
+        return fail(MK_EDEVICE, "circuit output descriptor upload failed");
+    return MK_OK;
+}
+
+__global__ void copy_words_kernel(const uint32_t *__restrict__ src, uint32_t *__restrict__ dst, size_t n) {
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < n) dst[idx] = src[idx];
+}
+
+// Device work of one evaluation, kernels only (so that it can be captured
+// into a graph): inputs into their wire slots, every level's
+// pre-combination, blind rotation and key switching, then the outputs.
+// gate_scratch holds abar | accumulator for the widest level.
+int enqueue_run(mk_ctx *ctx, const CircuitRun &R, uint32_t *gate_scratch, const uint32_t *in_dev,
+                uint32_t *out_dev, hipStream_t s) {
+    const mk_params &Pm = ctx->p;
+    const CircuitPlan &P = R.P;
+    const size_t batch = R.batch, stride = R.stride, words = R.words;
+    const int L = (int)P.levels.size() - 1;
+    if (R.n_inputs) {
+        const size_t n = (size_t)R.n_inputs * batch * stride;
+        hipLaunchKernelGGL(copy_words_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in_dev,
+                           R.wires + (size_t)P.level_base[0] * batch * stride, n);
+        if (hipGetLastError() != hipSuccess) return fail(MK_EDEVICE, "circuit input copy launch failed");
+    }
+    uint32_t *abar = gate_scratch;
+    uint32_t *acc = (uint32_t *)((char *)gate_scratch + R.abar_b);
+    const int log2_2N = __builtin_ctz(2 * Pm.N);
+    int rc;
+    for (int l = 1; l <= L; ++l) {
+        const size_t count = P.levels[l].size() * batch;
+        const size_t total = count * words;
+        {
+            StageTimer tm(ctx, 0, s);
+            hipLaunchKernelGGL(precombine_circuit_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256),
+                               0, s, R.d_desc + R.desc_off[l], (const uint32_t *)R.wires, batch, stride,
+                               (int)words, log2_2N, total, abar);
+        }
+        if (hipGetLastError() != hipSuccess) return fail(MK_EDEVICE, "circuit precombine launch failed");
+        if ((rc = run_blind_rotate(ctx, abar, acc, count, Pm.k * Pm.n, R.path, s)) ||
+            (rc = run_key_switch(ctx, acc, R.wires + (size_t)P.level_base[l] * batch * stride, count, stride,
+                                 R.path, s)))
+            return rc;
+    }
+    const size_t total = (size_t)R.n_outputs * batch * words;
+    {
+        StageTimer tm(ctx, 3, s);
+        hipLaunchKernelGGL(gather_outputs_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                           (const OutDesc *)R.d_od, (const uint32_t *)R.wires, out_dev, batch, stride,
+                           (int)words, total);
+    }
+    if (hipGetLastError() != hipSuccess) return fail(MK_EDEVICE, "circuit output gather launch failed");
+    return MK_OK;
+}
+
+void graph_release(mk_graph *g) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    bool any = false;
+    for (void *p : g->buf) any |= p != nullptr;
+    if (any) (void)hipDeviceSynchronize();
+    for (void *&p : g->buf) {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+    }
+    g->exec = nullptr;
+    g->graph = nullptr;
 }
 
 }  // namespace mk
@@ -297,114 +466,124 @@ int mk_circuit_stats(const mk_circuit *c, int32_t *n_levels, int64_t *live_gates
 
 int mk_eval_circuit(mk_ctx *ctx, const mk_circuit *c, const uint32_t *in_dev, uint32_t *out_dev,
                     size_t batch, size_t stride, int path, void *stream) {
-    if (!ctx) return fail(MK_EINVAL, "mk_eval_circuit: null context");
-    if (path != MK_PATH_I32 && path != MK_PATH_MFMA_I8) return fail(MK_EINVAL, "mk_eval_circuit: bad path");
-    const mk_params &Pm = ctx->p;
-    const size_t words = lwe_words(Pm);
-    if (stride < words) return fail(MK_EINVAL, "mk_eval_circuit: stride < kn+1");
-    if (!ctx->dev.uploaded) return fail(MK_ESTATE, "evaluation key not uploaded (mk_upload_eval_key)");
-    CircuitPlan P;
-    int rc = plan_circuit(c, P);
+    CircuitRun R;
+    int rc = build_run(ctx, c, batch, stride, path, R, "mk_eval_circuit");
     if (rc) return rc;
     if (!batch || !c->n_outputs) return MK_OK;
     if ((c->n_inputs && !in_dev) || !out_dev) return fail(MK_EINVAL, "mk_eval_circuit: null buffer");
     hipStream_t s = (hipStream_t)stream;
-    const int L = (int)P.levels.size() - 1;
-    // descriptors
-    std::vector<CircDesc> desc;
-    std::vector<size_t> desc_off(L + 2, 0);
-    for (int l = 1; l <= L; ++l) {
-        desc_off[l] = desc.size();
-        for (int gi : P.levels[l]) {
-            const mk_gate &g = c->gates[gi];
-            CircDesc d{-1, -1, 0, 0, kGateConst[g.type], 0};
-            const int sc[2] = {kGateS1[g.type], kGateS2[g.type]};
-            const int ins[2] = {g.in1, g.in2};
-            for (int q = 0; q < 2; ++q) {
-                const Ref &r = P.ref[ins[q]];
-                if (r.base < 0) {
-                    d.cst += (uint32_t)(sc[q] * r.cval) * 0x40000000u;
-                } else {
-                    int sv = sc[q];
-                    if (r.neg) {  // s * (1/4 - c)
-                        d.cst += (uint32_t)sv * 0x40000000u;
-                        sv = -sv;
-                    }
-                    (q == 0 ? d.slot1 : d.slot2) = P.slot[r.base];
-                    (q == 0 ? d.s1 : d.s2) = sv;
-                }
-            }
-            desc.push_back(d);
-        }
-    }
-    desc_off[L + 1] = desc.size();
-    std::vector<OutDesc> od(c->n_outputs);
-    for (int i = 0; i < c->n_outputs; ++i) {
-        const Ref &r = P.ref[c->outputs[i]];
-        od[i] = r.base < 0 ? OutDesc{-1, 0, (uint32_t)r.cval, 0}
-                           : OutDesc{P.slot[r.base], r.neg ? 1 : 0, 0, 0};
-    }
-    // device memory: wires | descriptors | output descriptors
-    const size_t wire_b = ((size_t)P.total_slots * batch * stride * 4 + 255) / 256 * 256;
-    const size_t desc_b = (desc.size() * sizeof(CircDesc) + 255) / 256 * 256;
-    const size_t od_b = od.size() * sizeof(OutDesc);
-    if ((rc = alloc_circ_scratch(ctx, wire_b + desc_b + od_b + 256))) return rc;
+    if ((rc = alloc_circ_scratch(ctx, R.wire_b + R.desc_b + R.od_b + 256))) return rc;
+    set_run_buffers(R, (char *)ctx->dev.circ_scratch);
     // after the first enqueue, errors wait for the stream before returning so
     // that no queued copy still reads the host descriptor vectors
-    auto bail = [&](int code, const char *msg) {
-        (void)hipStreamSynchronize(s);
-        return fail(code, msg);
-    };
-    char *base = (char *)ctx->dev.circ_scratch;
-    uint32_t *wires = (uint32_t *)base;
-    CircDesc *d_desc = (CircDesc *)(base + wire_b);
-    OutDesc *d_od = (OutDesc *)(base + wire_b + desc_b);
-    if (!desc.empty() && hipMemcpyAsync(d_desc, desc.data(), desc.size() * sizeof(CircDesc),
-                                        hipMemcpyHostToDevice, s) != hipSuccess)
-        return bail(MK_EDEVICE, "mk_eval_circuit: descriptor upload failed");
-    if (hipMemcpyAsync(d_od, od.data(), od_b, hipMemcpyHostToDevice, s) != hipSuccess)
-        return bail(MK_EDEVICE, "mk_eval_circuit: output descriptor upload failed");
-    if (c->n_inputs &&
-        hipMemcpyAsync(wires + (size_t)P.level_base[0] * batch * stride, in_dev,
-                       (size_t)c->n_inputs * batch * stride * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
-        return bail(MK_EDEVICE, "mk_eval_circuit: input copy failed");
-    // per-level pipeline; gate scratch sized for the widest level
-    const size_t maxc = (size_t)P.max_width * batch;
-    const size_t abar_b = (maxc * words * 4 + 255) / 256 * 256;
-    if ((rc = ensure_scratch(ctx, abar_b + maxc * (Pm.k + 1) * Pm.N * 4))) {
+    if ((rc = upload_descriptors(R, s))) {
         (void)hipStreamSynchronize(s);
         return rc;
     }
-    uint32_t *abar = (uint32_t *)ctx->dev.scratch;
-    uint32_t *acc = (uint32_t *)((char *)ctx->dev.scratch + abar_b);
-    const int log2_2N = __builtin_ctz(2 * Pm.N);
-    for (int l = 1; l <= L; ++l) {
-        const size_t count = P.levels[l].size() * batch;
-        const size_t total = count * words;
-        {
-            StageTimer tm(ctx, 0, s);
-            hipLaunchKernelGGL(precombine_circuit_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256),
-                               0, s, d_desc + desc_off[l], (const uint32_t *)wires, batch, stride,
-                               (int)words, log2_2N, total, abar);
-        }
-        if (hipGetLastError() != hipSuccess) return bail(MK_EDEVICE, "circuit precombine launch failed");
-        if ((rc = run_blind_rotate(ctx, abar, acc, count, Pm.k * Pm.n, path, s)) ||
-            (rc = run_key_switch(ctx, acc, wires + (size_t)P.level_base[l] * batch * stride, count, stride,
-                                 path, s))) {
-            (void)hipStreamSynchronize(s);
-            return rc;
-        }
+    if ((rc = ensure_scratch(ctx, R.gate_b))) {
+        (void)hipStreamSynchronize(s);
+        return rc;
     }
-    const size_t total = (size_t)c->n_outputs * batch * words;
-    {
-        StageTimer tm(ctx, 3, s);
-        hipLaunchKernelGGL(gather_outputs_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
-                           (const OutDesc *)d_od, (const uint32_t *)wires, out_dev, batch, stride,
-                           (int)words, total);
-    }
-    if (hipGetLastError() != hipSuccess) return bail(MK_EDEVICE, "circuit output gather launch failed");
+    rc = enqueue_run(ctx, R, (uint32_t *)ctx->dev.scratch, in_dev, out_dev, s);
     // the host descriptor vectors must outlive the asynchronous copies
-    if (hipStreamSynchronize(s) != hipSuccess) return fail(MK_EDEVICE, "mk_eval_circuit: stream sync failed");
+    const bool synced = hipStreamSynchronize(s) == hipSuccess;
+    if (rc) return rc;
+    if (!synced) return fail(MK_EDEVICE, "mk_eval_circuit: stream sync failed");
+    return MK_OK;
+}
+
+int mk_circuit_graph_create(mk_ctx *ctx, const mk_circuit *c, const uint32_t *in_dev, uint32_t *out_dev,
+                            size_t batch, size_t stride, int path, mk_graph **graph) {
+    if (!graph) return fail(MK_EINVAL, "mk_circuit_graph_create: null graph pointer");
+    *graph = nullptr;
+    CircuitRun R;
+    int rc = build_run(ctx, c, batch, stride, path, R, "mk_circuit_graph_create");
+    if (rc) return rc;
+    if (!batch || !c->n_outputs) return fail(MK_EINVAL, "mk_circuit_graph_create: empty batch or circuit");
+    if ((c->n_inputs && !in_dev) || !out_dev) return fail(MK_EINVAL, "mk_circuit_graph_create: null buffer");
+    mk_graph *g = new (std::nothrow) mk_graph();
+    if (!g) return fail(MK_ENOMEM, "mk_circuit_graph_create: out of host memory");
+    g->ctx = ctx;
+    g->levels = (int)R.P.levels.size() - 1;
+    g->gates = R.P.live_gates * (int64_t)batch;
+    auto abandon = [&](int code) {
+        graph_release(g);
+        delete g;
+        return code;
+    };
+    // graph-owned device memory: wires | descriptors, the gate pipeline's
+    // scratch and, on the MFMA path, the rotation's and key switch's scratch
+    const size_t maxc = (size_t)R.P.max_width * batch;
+    const size_t sizes[4] = {R.wire_b + R.desc_b + R.od_b + 256, R.gate_b,
+                             path == MK_PATH_MFMA_I8 ? mfma_scratch_need(ctx->p, maxc) : 0,
+                             path == MK_PATH_MFMA_I8 ? ks_scratch_need(ctx->p, maxc) : 0};
+    for (int i = 0; i < 4; ++i) {
+        g->bytes[i] = sizes[i];
+        if (sizes[i] && hipMalloc(&g->buf[i], sizes[i]) != hipSuccess) {
+            g->buf[i] = nullptr;
+            return abandon(fail(MK_ENOMEM, "mk_circuit_graph_create: device allocation failed"));
+        }
+    }
+    set_run_buffers(R, (char *)g->buf[0]);
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+        return abandon(fail(MK_EDEVICE, "mk_circuit_graph_create: stream creation failed"));
+    if ((rc = upload_descriptors(R, cs)) || hipStreamSynchronize(cs) != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        return abandon(rc ? rc : fail(MK_EDEVICE, "mk_circuit_graph_create: descriptor upload failed"));
+    }
+    // capture with the context's scratch pointing at the graph's buffers (no
+    // allocation can happen inside the capture) and profiling off
+    DeviceKeys &D = ctx->dev;
+    void *save_p[3] = {D.scratch, D.mfma_scratch, D.ks_scratch};
+    size_t save_b[3] = {D.scratch_bytes, D.mfma_scratch_bytes, D.ks_scratch_bytes};
+    const int save_prof = D.profiling;
+    D.scratch = g->buf[1]; D.scratch_bytes = g->bytes[1];
+    D.mfma_scratch = g->buf[2]; D.mfma_scratch_bytes = g->bytes[2];
+    D.ks_scratch = g->buf[3]; D.ks_scratch_bytes = g->bytes[3];
+    D.profiling = 0;
+    hipGraph_t graph_raw = nullptr;
+    rc = MK_OK;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        rc = fail(MK_EDEVICE, "mk_circuit_graph_create: capture failed to start");
+    } else {
+        rc = enqueue_run(ctx, R, (uint32_t *)g->buf[1], in_dev, out_dev, cs);
+        const hipError_t e = hipStreamEndCapture(cs, &graph_raw);
+        if (!rc && e != hipSuccess) rc = fail(MK_EDEVICE, "mk_circuit_graph_create: capture failed");
+    }
+    D.scratch = save_p[0]; D.scratch_bytes = save_b[0];
+    D.mfma_scratch = save_p[1]; D.mfma_scratch_bytes = save_b[1];
+    D.ks_scratch = save_p[2]; D.ks_scratch_bytes = save_b[2];
+    D.profiling = save_prof;
+    (void)hipStreamDestroy(cs);
+    g->graph = graph_raw;
+    if (rc) return abandon(rc);
+    if (hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess) {
+        g->exec = nullptr;
+        return abandon(fail(MK_EDEVICE, "mk_circuit_graph_create: instantiation failed"));
+    }
+    *graph = g;
+    return MK_OK;
+}
+
+int mk_graph_launch(mk_graph *g, void *stream) {
+    if (!g || !g->exec) return fail(MK_EINVAL, "mk_graph_launch: null graph");
+    if (hipGraphLaunch(g->exec, (hipStream_t)stream) != hipSuccess)
+        return fail(MK_EDEVICE, "mk_graph_launch: launch failed");
+    return MK_OK;
+}
+
+int mk_graph_info(const mk_graph *g, int32_t *n_levels, int64_t *gates) {
+    if (!g) return fail(MK_EINVAL, "mk_graph_info: null graph");
+    if (n_levels) *n_levels = g->levels;
+    if (gates) *gates = g->gates;
+    return MK_OK;
+}
+
+int mk_graph_destroy(mk_graph *g) {
+    if (!g) return MK_OK;
+    graph_release(g);
+    delete g;
     return MK_OK;
 }
 

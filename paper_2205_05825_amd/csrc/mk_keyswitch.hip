@@ -286,6 +286,10 @@ __global__ __launch_bounds__(256, 2) void ks_gemm_kernel(const int8_t *__restric
     }
 }
 
+size_t ks_scratch_need(const mk_params &P, size_t count) {
+    return (size_t)P.k * P.N * ((count + 31) / 32 * 32) * 4;
+}
+
 int launch_ks_mfma(mk_ctx *ctx, const uint32_t *acc, uint32_t *out, size_t count, size_t stride,
                    hipStream_t s) {
     const mk_params &P = ctx->p;
@@ -294,7 +298,7 @@ int launch_ks_mfma(mk_ctx *ctx, const uint32_t *acc, uint32_t *out, size_t count
     const KsShape sh = ks_shape(P, GP);
     if (P.N < kKsRing || (size_t)P.N * GP * 4 >= ((size_t)1 << 31))
         return fail(MK_EINVAL, "int8-MFMA key switching: batch too large for one launch (split it)");
-    const size_t need = (size_t)P.k * P.N * GP * 4;
+    const size_t need = ks_scratch_need(P, count);
     if (D.ks_scratch_bytes < need) {
         if (D.ks_scratch) {
             MK_HIP(hipStreamSynchronize(s), "ks scratch sync");

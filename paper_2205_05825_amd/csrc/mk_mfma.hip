@@ -879,6 +879,14 @@ __global__ void mfma_copyout_kernel(const uint32_t *__restrict__ src, uint32_t *
 
 static inline unsigned blocks(size_t threads, int per) { return (unsigned)((threads + per - 1) / per); }
 
+// Scratch bytes of the rotation for `count` gates: accumulator, partial
+// sums W, digits U and V.
+size_t mfma_scratch_need(const mk_params &P, size_t count) {
+    const size_t GP = (count + 31) / 32 * 32;
+    const size_t K1 = P.k + 1, N = P.N, ell = P.bk_ell;
+    return GP * K1 * N * 4 + K1 * GP * N * 4 + K1 * ell * GP * N + ell * GP * N;
+}
+
 // Allocates (grows) the MFMA scratch for `count` gates and fills the kernel
 // arguments.
 static int prepare(mk_ctx *ctx, const uint32_t *abar, size_t count, hipStream_t s, MfmaArgs &a) {
@@ -887,12 +895,12 @@ static int prepare(mk_ctx *ctx, const uint32_t *abar, size_t count, hipStream_t 
     const size_t GP = (count + 31) / 32 * 32;
     const int K1 = P.k + 1, N = P.N, ell = P.bk_ell;
     const size_t acc_b = GP * K1 * N * 4, w_b = (size_t)K1 * GP * N * 4;
-    const size_t u_b = (size_t)K1 * ell * GP * N, v_b = (size_t)ell * GP * N;
+    const size_t u_b = (size_t)K1 * ell * GP * N;
     // the GEMMs address a key polynomial's digit block with 32-bit offsets
     if (u_b >= ((size_t)1 << 31))
         return fail(MK_EINVAL, "int8-MFMA path: batch too large for one launch (split it)");
     DeviceKeys &D = ctx->dev;
-    const size_t need = acc_b + w_b + u_b + v_b;
+    const size_t need = mfma_scratch_need(P, count);
     if (D.mfma_scratch_bytes < need) {
         if (D.mfma_scratch) {
             MK_HIP(hipStreamSynchronize(s), "mfma scratch sync");

@@ -108,3 +108,41 @@ def test_lr_step_small(torch_cuda):
     got = _eval(torch_cuda, ctx, circ, in_ct, 1)
     dec = np.stack([tfhe.decrypt(K, o) for o in got])[:, 0]
     assert np.array_equal(mi.from_bits(dec.reshape(2, 16)), lr.replica_step(X, y, w))
+
+
+@pytest.mark.parametrize("path", [0, 1])
+def test_graph_replays_match_eager(torch_cuda, path):
+    """An operator captured as a HIP graph: three replays on new inputs, with
+    eager evaluations on the same stream in between; every replay equals the
+    eager result word for word and decrypts to the integer results."""
+    import paper_2205_05825_amd as mk
+    K, ctx = helpers.gpu_world("C1B")
+    k = 4
+    circ = mk.build_operator(0, k)                      # 4-bit adder
+    d = torch_cuda.device("cuda:0")
+    W = K.params.lwe_words + 2                          # padded rows
+    batch = 5
+    inp = torch_cuda.zeros((2 * k, batch, W), dtype=torch_cuda.int32, device=d)
+    out = torch_cuda.full((len(circ.outputs), batch, W), -1, dtype=torch_cuda.int32, device=d)
+    g = ctx.circuit_graph(circ, inp, out, path=path)
+    try:
+        levels, gates = g.info()
+        assert levels >= 1 and gates == batch * mk.circuit_stats(circ)[1]
+        rng = np.random.default_rng(70 + path)
+        for rep in range(3):
+            a = rng.integers(-8, 8, batch)
+            b = rng.integers(-8, 8, batch)
+            in_ct = np.concatenate([helpers.encrypt_operands(K, a, k, 0, 700 + rep),
+                                    helpers.encrypt_operands(K, b, k, 1, 710 + rep)])
+            padded = np.zeros((2 * k, batch, W), np.uint32)
+            padded[:, :, :in_ct.shape[2]] = in_ct
+            inp.copy_(torch_cuda.from_numpy(padded.view(np.int32)).to(d))
+            g.launch()
+            torch_cuda.cuda.synchronize()
+            got = out.cpu().numpy().view(np.uint32).copy()
+            eager = _eval(torch_cuda, ctx, circ, padded, path)     # eager work in between
+            assert np.array_equal(got[:, :, :K.params.lwe_words], eager[:, :, :K.params.lwe_words]), rep
+            dec = np.stack([tfhe.decrypt(K, o[:, :K.params.lwe_words]) for o in got])
+            assert np.array_equal(mi.from_bits(dec.T), _wrap(a + b, k)), rep
+    finally:
+        g.close()

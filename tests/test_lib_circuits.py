@@ -5,6 +5,8 @@ import pytest
 
 from oracle import circuits as C
 from oracle import lr
+from oracle import params as OP
+from tests import helpers
 
 
 def _same(lib, ora):
@@ -55,3 +57,22 @@ def test_engine_rejects_malformed_netlists():
     dup = mk.Circuit(good.n_wires, np.array([2, 2, 3, 4]), good.outputs, good.gates)
     with pytest.raises(mk.MkError):
         mk.circuit_stats(dup)
+
+
+def test_graph_entry_points_without_a_device_key():
+    """Graph creation refuses a context whose key is not uploaded (checked on
+    the host, before any device work); destroying a null graph is a no-op."""
+    import ctypes
+    import paper_2205_05825_amd as mk
+    from paper_2205_05825_amd import _lib
+    ctx = mk.Context(helpers.lib_params(OP.C1B), 3)
+    circ = mk.build_operator(mk.OP_ADD, 2)
+    h = ctypes.c_void_p()
+    rc = _lib._L.mk_circuit_graph_create(ctx._h, ctypes.byref(circ.c()), ctypes.c_void_p(16),
+                                         ctypes.c_void_p(16), 4, OP.C1B.lwe_words, 1,
+                                         ctypes.byref(h))
+    assert rc == -4 and not h.value
+    assert _lib._L.mk_circuit_graph_create(ctx._h, ctypes.byref(circ.c()), None, None, 4,
+                                           OP.C1B.lwe_words, 1, None) == -1
+    assert _lib._L.mk_graph_destroy(None) == 0
+    assert _lib._L.mk_graph_launch(None, None) == -1
