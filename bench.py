@@ -43,10 +43,17 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "mfma_gemm1_c2_1024gates_hbm_tr
 MFMA_SOURCE = os.path.join(ROOT, "paper_2205_05825_amd", "csrc", "mk_mfma.hip")
 
 
-def measured_traffic():
-    """HBM bytes per stage-1 GEMM launch from the committed rocprofv3
-    FETCH_SIZE/WRITE_SIZE summary, or None when the kernel source changed
-    since those counters were taken."""
+# Stage-1 GEMM instantiation run for each tile shape (the shape table of
+# mk_mfma.hip), as rocprofv3 names the kernel.
+GEMM1_KERNEL = {0: "mfma_gemm1_limb_kernel<8, 1, 2>", 1: "mfma_gemm1_limb_kernel<4, 2, 2>",
+                2: "mfma_gemm1_limb_kernel<4, 1, 3>", 3: "mfma_gemm1_kernel<2, 1, 2>",
+                4: "mfma_gemm1_limb_kernel<8, 2, 1>"}
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE summary, or None when that kernel was not measured
+    or its source changed since the counters were taken."""
     import hashlib
     import re
     try:
@@ -54,7 +61,7 @@ def measured_traffic():
         src = hashlib.sha256(open(MFMA_SOURCE, "rb").read()).hexdigest()
     except OSError:
         return None
-    m = re.search(r"HBM bytes per launch: (\d+)", text)
+    m = re.search(r"HBM bytes per launch \[%s\]: (\d+)" % re.escape(kernel), text)
     h = re.search(r"sha256 ([0-9a-f]{64})", text)
     if not m or not h or h.group(1) != src:
         return None
@@ -112,6 +119,8 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--path", choices=["mfma", "i32"], default="mfma")
     ap.add_argument("--cpu-gates-per-core", type=int, default=1)
+    ap.add_argument("--tiles", default="", metavar="G1,G2",
+                    help="force the two GEMM tile shapes instead of autotuning")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run one device-to-device copy of MIB MiB (reference "
@@ -159,6 +168,10 @@ def main():
     head = paths[args.path]
     # the autotuner times every GEMM tile shape for this batch size
     tiles = ctx.autotune(BATCH)
+    if args.tiles:
+        v1, v2 = (int(x) for x in args.tiles.split(","))
+        ctx.set_tiles(v1, v2)
+        tiles = (v1, v2, tiles[2])
     # correctness gate before timing: outputs decrypt and both paths agree
     outs = {}
     for name, path in paths.items():
@@ -207,11 +220,12 @@ def main():
         g1_ops = 8 * (sum(2 * lv * ell for lv in live) / k) * N * N * BATCH
         g1_ms = ms[4] / max(ln[4], 1)
         achieved = g1_ops / (g1_ms * 1e-3)
+        kname = GEMM1_KERNEL[tiles[0]]
         roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_INT8_OPS / 1e12,
-                "unit": "TOP/s", "frac": achieved / PEAK_INT8_OPS, "traffic": measured_traffic(),
+                "unit": "TOP/s", "frac": achieved / PEAK_INT8_OPS, "traffic": measured_traffic(kname),
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                                 "copy-calibrated)",
-                "kernel": "mfma_gemm1_kernel", "avg_launch_ms": g1_ms,
+                "kernel": kname, "avg_launch_ms": g1_ms,
                 "launches": ln[4],
                 "whole_rotation_tops": 8 * macs / (br_ms * 1e-3) / 1e12}
     else:
@@ -228,7 +242,8 @@ def main():
         "config": {"workload": "1024 mixed bootstrapped MK gates (AND/OR/NOR/XOR/XNOR/NAND), "
                                "k=2 n=560 N=1024 B=2^8 ell=3 B'=2^2 t=8",
                    "global_batch": BATCH, "path": args.path, "parallelism": "single GPU"},
-        "tiles": {"gemm1_shape": tiles[0], "gemm2_shape": tiles[1], "candidate_ms": tiles[2]},
+        "tiles": {"gemm1_shape": tiles[0], "gemm2_shape": tiles[1], "candidate_ms": tiles[2],
+                  "sub_batches": ctx.get_split(BATCH)},
         "stage_ms_per_step": {"precombine": ms[0], "blind_rotate": ms[1],
                               "extract_keyswitch": ms[2], "mfma_gemm1": ms[4], "mfma_gemm2": ms[5],
                               "rotdec": ms[6], "wdec": ms[7]},

@@ -284,13 +284,25 @@ int mk_get_profile(mk_ctx *ctx, double *ms, int64_t *launches, int reset);
  *                 records the fastest for that batch size; ms (optional,
  *                 2 * MK_TILE_SHAPES floats) receives the average times,
  *                 gemm1 shapes first (0 for shapes that do not divide N/32).
+ *                 It then tunes the shapes for half the batch and times a
+ *                 few CMux steps of the whole batch run in one piece and as
+ *                 two sub-batches on two streams (one's digit kernels and
+ *                 GEMM tails overlapping the other's GEMMs), and records
+ *                 the faster batch split for this size.
  *   mk_set_tiles  forces shapes (-1 = use the tuned or default shape).
  *   mk_get_tiles  reports the shapes a batch of `count` gates would use.
+ *   mk_set_split  records the split of batches of `count` gates: 1 (whole),
+ *                 2 (two sub-batches; needs count > 32) or 0 (forget).
+ *   mk_get_split  reports it (1 unless tuned or set).  Splitting is skipped
+ *                 at profiling level 2 and while `stream` is being captured
+ *                 into a graph; results are identical either way.
  * Errors: MK_EINVAL, MK_ESTATE (key not uploaded), MK_ENOMEM, MK_EDEVICE. */
 #define MK_TILE_SHAPES 5
 int mk_autotune(mk_ctx *ctx, size_t count, void *stream, int32_t *gemm1_shape,
                 int32_t *gemm2_shape, float *ms);
 int mk_set_tiles(mk_ctx *ctx, int gemm1_shape, int gemm2_shape);
+int mk_set_split(mk_ctx *ctx, size_t count, int parts);
+int mk_get_split(const mk_ctx *ctx, size_t count, int32_t *parts);
 int mk_get_tiles(const mk_ctx *ctx, size_t count, int32_t *gemm1_shape,
                  int32_t *gemm2_shape);
 

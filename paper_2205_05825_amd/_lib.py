@@ -77,6 +77,8 @@ _SIGS = {
     "mk_circuit_stats": ([ctypes.POINTER(MkCircuit), ctypes.POINTER(ctypes.c_int32),
                           ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
                           ctypes.POINTER(ctypes.c_int32)], _i),
+    "mk_set_split": ([_vp, _sz, _i], _i),
+    "mk_get_split": ([_vp, _sz, ctypes.POINTER(ctypes.c_int32)], _i),
     "mk_autotune": ([_vp, _sz, _vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                      ctypes.POINTER(ctypes.c_float)], _i),
     "mk_set_tiles": ([_vp, _i, _i], _i),
@@ -216,6 +218,14 @@ class Context:
 
     def set_tiles(self, gemm1_shape: int = -1, gemm2_shape: int = -1):
         _check(_L.mk_set_tiles(self._h, gemm1_shape, gemm2_shape))
+
+    def set_split(self, count: int, parts: int):
+        _check(_L.mk_set_split(self._h, count, parts))
+
+    def get_split(self, count: int) -> int:
+        p = ctypes.c_int32()
+        _check(_L.mk_get_split(self._h, count, ctypes.byref(p)))
+        return p.value
 
     def get_tiles(self, count: int):
         v1, v2 = ctypes.c_int32(), ctypes.c_int32()

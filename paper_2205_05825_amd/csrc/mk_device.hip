@@ -107,12 +107,18 @@ void device_release(mk_ctx *ctx) {
         for (void *p : ptrs)
             if (p) (void)hipFree(p);
     }
+    for (void *&st : D.aux_stream)
+        if (st) (void)hipStreamDestroy((hipStream_t)st);
+    for (void *&ev : D.aux_event)
+        if (ev) (void)hipEventDestroy((hipEvent_t)ev);
     const int prof = D.profiling;
     const auto tuned = D.tuned_tiles;
+    const auto tuned_parts = D.tuned_parts;
     const int f0 = D.force_tiles[0], f1 = D.force_tiles[1];
     D = DeviceKeys();
     D.profiling = prof;
     D.tuned_tiles = tuned;
+    D.tuned_parts = tuned_parts;
     D.force_tiles[0] = f0;
     D.force_tiles[1] = f1;
 }

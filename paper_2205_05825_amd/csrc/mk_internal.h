@@ -59,6 +59,11 @@ struct DeviceKeys {
     // 32-gate tiles) and optionally forced (-1 = not forced).
     std::map<int, std::pair<int, int>> tuned_tiles;
     int force_tiles[2] = {-1, -1};
+    // Sub-batches of the MFMA rotation (1 or 2, run on aux streams), tuned
+    // per batch size in 32-gate tiles; streams and events made on first use.
+    std::map<int, int> tuned_parts;
+    void *aux_stream[2] = {nullptr, nullptr};
+    void *aux_event[3] = {nullptr, nullptr, nullptr};
 };
 
 }  // namespace mk

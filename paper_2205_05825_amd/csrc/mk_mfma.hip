@@ -887,23 +887,45 @@ size_t mfma_scratch_need(const mk_params &P, size_t count) {
     return GP * K1 * N * 4 + K1 * GP * N * 4 + K1 * ell * GP * N + ell * GP * N;
 }
 
-// Allocates (grows) the MFMA scratch for `count` gates and fills the kernel
-// arguments.
-static int prepare(mk_ctx *ctx, const uint32_t *abar, size_t count, hipStream_t s, MfmaArgs &a) {
+// Sub-batches of a rotation: a batch can be split in two halves that run on
+// two streams, so that one half's memory-bound digit kernels and GEMM tails
+// overlap the other half's GEMMs.  The split is chosen by the autotuner per
+// batch size; untuned batches are not split.
+struct Split {
+    int parts;
+    size_t cnt[2], off[2];
+};
+static Split split_for(const mk_ctx *ctx, size_t count) {
+    Split sp{1, {count, 0}, {0, 0}};
+    const int GT = (int)((count + 31) / 32);
+    auto it = ctx->dev.tuned_parts.find(GT);
+    if (it != ctx->dev.tuned_parts.end() && it->second == 2 && GT >= 2) {
+        sp.parts = 2;
+        sp.cnt[0] = (size_t)((GT + 1) / 2) * 32;
+        sp.cnt[1] = count - sp.cnt[0];
+        sp.off[1] = sp.cnt[0];
+    }
+    return sp;
+}
+
+// Allocates (grows) the MFMA scratch for the parts of `sp` and fills their
+// kernel arguments (part i: gates off[i] .. off[i] + cnt[i] - 1).
+static int prepare(mk_ctx *ctx, const uint32_t *abar, const Split &sp, hipStream_t s, MfmaArgs *a) {
     const mk_params &P = ctx->p;
     if (P.N < kDigCoef) return fail(MK_EPARAM, "int8-MFMA path needs N >= 128");
-    const size_t GP = (count + 31) / 32 * 32;
     const int K1 = P.k + 1, N = P.N, ell = P.bk_ell;
-    const size_t acc_b = GP * K1 * N * 4, w_b = (size_t)K1 * GP * N * 4;
-    const size_t u_b = (size_t)K1 * ell * GP * N;
-    // the GEMMs address a key polynomial's digit block with 32-bit offsets
-    if (u_b >= ((size_t)1 << 31))
-        return fail(MK_EINVAL, "int8-MFMA path: batch too large for one launch (split it)");
+    size_t need = 0;
+    for (int i = 0; i < sp.parts; ++i) {
+        const size_t GP = (sp.cnt[i] + 31) / 32 * 32;
+        // the GEMMs address a key polynomial's digit block with 32-bit offsets
+        if ((size_t)K1 * ell * GP * N >= ((size_t)1 << 31))
+            return fail(MK_EINVAL, "int8-MFMA path: batch too large for one launch (split it)");
+        need += mfma_scratch_need(P, sp.cnt[i]);
+    }
     DeviceKeys &D = ctx->dev;
-    const size_t need = mfma_scratch_need(P, count);
     if (D.mfma_scratch_bytes < need) {
         if (D.mfma_scratch) {
-            MK_HIP(hipStreamSynchronize(s), "mfma scratch sync");
+            MK_HIP(hipDeviceSynchronize(), "mfma scratch sync");
             (void)hipFree(D.mfma_scratch);
             D.mfma_scratch = nullptr;
             D.mfma_scratch_bytes = 0;
@@ -914,17 +936,24 @@ static int prepare(mk_ctx *ctx, const uint32_t *abar, size_t count, hipStream_t 
         }
         D.mfma_scratch_bytes = need;
     }
-    char *sp = (char *)D.mfma_scratch;
-    a.k = P.k; a.n = P.n; a.N = N; a.ell = ell; a.log2N = __builtin_ctz(N);
-    a.GP = (int)GP; a.G = (int)count;
-    a.offset = decomp_offset(ell);
-    a.abar = abar;
-    a.acc = (uint32_t *)sp;
-    a.W = (uint32_t *)(sp + acc_b);
-    a.U = (int8_t *)(sp + acc_b + w_b);
-    a.V = (int8_t *)(sp + acc_b + w_b + u_b);
-    a.bk = D.bk_win;
-    a.evk = D.evk_win;
+    char *sp_base = (char *)D.mfma_scratch;
+    for (int i = 0; i < sp.parts; ++i) {
+        const size_t GP = (sp.cnt[i] + 31) / 32 * 32;
+        const size_t acc_b = GP * K1 * N * 4, w_b = (size_t)K1 * GP * N * 4;
+        const size_t u_b = (size_t)K1 * ell * GP * N;
+        MfmaArgs &x = a[i];
+        x.k = P.k; x.n = P.n; x.N = N; x.ell = ell; x.log2N = __builtin_ctz(N);
+        x.GP = (int)GP; x.G = (int)sp.cnt[i];
+        x.offset = decomp_offset(ell);
+        x.abar = abar ? abar + sp.off[i] * ((size_t)P.k * P.n + 1) : nullptr;
+        x.acc = (uint32_t *)sp_base;
+        x.W = (uint32_t *)(sp_base + acc_b);
+        x.U = (int8_t *)(sp_base + acc_b + w_b);
+        x.V = (int8_t *)(sp_base + acc_b + w_b + u_b);
+        x.bk = D.bk_win;
+        x.evk = D.evk_win;
+        sp_base += mfma_scratch_need(P, sp.cnt[i]);
+    }
     return MK_OK;
 }
 
@@ -949,72 +978,125 @@ static void shapes_for(const mk_ctx *ctx, int GT, int &v1, int &v2) {
     if (D.force_tiles[1] >= 0) v2 = D.force_tiles[1];
 }
 
-int launch_br_mfma(mk_ctx *ctx, const uint32_t *abar, uint32_t *acc_out, size_t count, int steps,
-                   hipStream_t s) {
+// Enqueues CMux steps st0 .. st1-1 of every part, part i on stream ss[i].
+static int enqueue_steps(mk_ctx *ctx, const MfmaArgs *a, int parts, hipStream_t *ss, int st0, int st1) {
     const mk_params &P = ctx->p;
-    MfmaArgs a;
-    int rc = prepare(ctx, abar, count, s, a);
-    if (rc) return rc;
-    const int K1 = P.k + 1, N = P.N;
-    const size_t GP = (size_t)a.GP;
-    const int NB = N / 32, GT = (int)(GP / 32);
-    int v1, v2;
-    shapes_for(ctx, GT, v1, v2);
-    {
-        StageTimer tm(ctx, 1, s);
-        hipLaunchKernelGGL(mfma_init_kernel, dim3(blocks(GP * K1 * N, 256)), dim3(256), 0, s, a);
-        MK_HIP(hipGetLastError(), "mfma init launch");
-        const int KG = NB / kDigKB;
-        const unsigned wd_blocks = (unsigned)(GT * KG);
-        for (int st = 0; st < steps; ++st) {
-            const int party = st / P.n, bit = st % P.n;
-            // ACC starts as (X^-b v, 0, .., 0) and during party i's steps only
-            // c'_0 and c'_{1+i} receive stage-2 output, while c'_j = 0 whenever
-            // ACC_j = 0 (its digits are all zero).  So slots j >= i+2 are still
-            // exactly zero: their digits, products and partial sums are skipped.
-            const int live = std::min(K1, party + 2);
-            const unsigned rd_blocks = (unsigned)(live * GT * KG);
+    const int K1 = P.k + 1, NB = P.N / 32, KG = NB / kDigKB;
+    int GT[2], v1[2], v2[2];
+    for (int i = 0; i < parts; ++i) {
+        GT[i] = a[i].GP / 32;
+        shapes_for(ctx, GT[i], v1[i], v2[i]);
+    }
+    for (int st = st0; st < st1; ++st) {
+        const int party = st / P.n, bit = st % P.n;
+        // ACC starts as (X^-b v, 0, .., 0) and during party i's steps only
+        // c'_0 and c'_{1+i} receive stage-2 output, while c'_j = 0 whenever
+        // ACC_j = 0 (its digits are all zero).  So slots j >= i+2 are still
+        // exactly zero: their digits, products and partial sums are skipped.
+        const int live = std::min(K1, party + 2);
+        for (int i = 0; i < parts; ++i) {
+            hipStream_t s = ss[i];
             {
                 StageTimer t6(ctx, 6, s);
-                hipLaunchKernelGGL(mfma_rotdec_kernel, dim3(rd_blocks), dim3(256), 0, s, a, st);
+                hipLaunchKernelGGL(mfma_rotdec_kernel, dim3((unsigned)(live * GT[i] * KG)), dim3(256), 0, s,
+                                   a[i], st);
             }
             {
                 StageTimer t4(ctx, 4, s);
-                gemm1(v1, a, party, bit, live, GT, NB, s);
+                gemm1(v1[i], a[i], party, bit, live, GT[i], NB, s);
             }
             {
                 StageTimer t7(ctx, 7, s);
-                hipLaunchKernelGGL(mfma_wdec_kernel, dim3(wd_blocks), dim3(256), 0, s, a, live);
+                hipLaunchKernelGGL(mfma_wdec_kernel, dim3((unsigned)(GT[i] * KG)), dim3(256), 0, s, a[i],
+                                   live);
             }
             {
                 StageTimer t5(ctx, 5, s);
-                gemm2(v2, a, party, bit, GT, NB, s);
+                gemm2(v2[i], a[i], party, bit, GT[i], NB, s);
             }
         }
-        MK_HIP(hipGetLastError(), "mfma step launch");
-        hipLaunchKernelGGL(mfma_copyout_kernel, dim3(blocks(count * K1 * N, 256)), dim3(256), 0, s,
-                           a.acc, acc_out, count * K1 * N);
-        MK_HIP(hipGetLastError(), "mfma copyout launch");
+    }
+    MK_HIP(hipGetLastError(), "mfma step launch");
+    return MK_OK;
+}
+
+// Streams for the parts: the caller's stream when not split; otherwise two
+// auxiliary streams (default priority) that wait for the caller's stream
+// and that the caller's stream later waits for (join_parts).
+static int fork_parts(mk_ctx *ctx, int parts, hipStream_t s, hipStream_t *ss) {
+    if (parts == 1) {
+        ss[0] = s;
+        return MK_OK;
+    }
+    DeviceKeys &D = ctx->dev;
+    for (int i = 0; i < 2; ++i)
+        if (!D.aux_stream[i])
+            MK_HIP(hipStreamCreateWithFlags((hipStream_t *)&D.aux_stream[i], hipStreamNonBlocking), "aux stream");
+    for (int i = 0; i < 3; ++i)
+        if (!D.aux_event[i])
+            MK_HIP(hipEventCreateWithFlags((hipEvent_t *)&D.aux_event[i], hipEventDisableTiming), "aux event");
+    MK_HIP(hipEventRecord((hipEvent_t)D.aux_event[0], s), "fork record");
+    for (int i = 0; i < 2; ++i) {
+        ss[i] = (hipStream_t)D.aux_stream[i];
+        MK_HIP(hipStreamWaitEvent(ss[i], (hipEvent_t)D.aux_event[0], 0), "fork wait");
+    }
+    return MK_OK;
+}
+static int join_parts(mk_ctx *ctx, int parts, hipStream_t s, hipStream_t *ss) {
+    if (parts == 1) return MK_OK;
+    DeviceKeys &D = ctx->dev;
+    for (int i = 0; i < 2; ++i) {
+        MK_HIP(hipEventRecord((hipEvent_t)D.aux_event[1 + i], ss[i]), "join record");
+        MK_HIP(hipStreamWaitEvent(s, (hipEvent_t)D.aux_event[1 + i], 0), "join wait");
     }
     return MK_OK;
 }
 
-// Times every tile shape of both GEMMs on the scratch buffers of a batch of
-// `count` gates (contents irrelevant: only durations are read) and records
-// the fastest for this batch size.
-int autotune(mk_ctx *ctx, size_t count, hipStream_t s, int *v1_out, int *v2_out, float *ms_out) {
+int launch_br_mfma(mk_ctx *ctx, const uint32_t *abar, uint32_t *acc_out, size_t count, int steps,
+                   hipStream_t s) {
+    const mk_params &P = ctx->p;
+    Split sp = split_for(ctx, count);
+    // per-kernel timing and graph capture see a single stream
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (ctx->dev.profiling >= 2 || hipStreamIsCapturing(s, &cap) != hipSuccess ||
+        cap != hipStreamCaptureStatusNone)
+        sp = Split{1, {count, 0}, {0, 0}};
+    MfmaArgs a[2];
+    int rc = prepare(ctx, abar, sp, s, a);
+    if (rc) return rc;
+    const int K1 = P.k + 1, N = P.N;
+    StageTimer tm(ctx, 1, s);
+    hipStream_t ss[2];
+    if ((rc = fork_parts(ctx, sp.parts, s, ss))) return rc;
+    for (int i = 0; i < sp.parts; ++i) {
+        hipLaunchKernelGGL(mfma_init_kernel, dim3(blocks((size_t)a[i].GP * K1 * N, 256)), dim3(256), 0, ss[i],
+                           a[i]);
+        MK_HIP(hipGetLastError(), "mfma init launch");
+    }
+    if ((rc = enqueue_steps(ctx, a, sp.parts, ss, 0, steps))) return rc;
+    for (int i = 0; i < sp.parts; ++i) {
+        const size_t words = sp.cnt[i] * K1 * N;
+        hipLaunchKernelGGL(mfma_copyout_kernel, dim3(blocks(words, 256)), dim3(256), 0, ss[i], a[i].acc,
+                           acc_out + sp.off[i] * K1 * N, words);
+        MK_HIP(hipGetLastError(), "mfma copyout launch");
+    }
+    return join_parts(ctx, sp.parts, s, ss);
+}
+
+// Times every tile shape of both GEMMs on the scratch buffers of `count`
+// gates (contents irrelevant: only durations are read) and records the
+// fastest for that batch size.
+static int tune_shapes(mk_ctx *ctx, size_t count, hipStream_t s, hipEvent_t e0, hipEvent_t e1, int *pick,
+                       float *ms_out) {
     const mk_params &P = ctx->p;
     MfmaArgs a;
-    int rc = prepare(ctx, nullptr, count, s, a);
+    int rc = prepare(ctx, nullptr, Split{1, {count, 0}, {0, 0}}, s, &a);
     if (rc) return rc;
     const int NB = P.N / 32, GT = a.GP / 32;
     const int party = P.k - 1, live = std::min(P.k + 1, party + 2);
-    hipEvent_t e0, e1;
-    MK_HIP(hipEventCreate(&e0), "autotune event");
-    MK_HIP(hipEventCreate(&e1), "autotune event");
     constexpr int kReps = 4;
     float best[2] = {3.0e38f, 3.0e38f};
-    int pick[2] = {0, 0};
+    pick[0] = pick[1] = default_shape(NB);
     for (int which = 0; which < 2; ++which)
         for (int v = 0; v < kNumShapes; ++v) {
             if (NB % kShapes[v].MR) continue;
@@ -1023,25 +1105,91 @@ int autotune(mk_ctx *ctx, size_t count, hipStream_t s, int *v1_out, int *v2_out,
                 else gemm2(v, a, party, 0, GT, NB, s);
             };
             run();  // warm-up
-            (void)hipEventRecord(e0, s);
+            MK_HIP(hipEventRecord(e0, s), "autotune record");
             for (int r = 0; r < kReps; ++r) run();
-            (void)hipEventRecord(e1, s);
+            MK_HIP(hipEventRecord(e1, s), "autotune record");
             float ms = 0;
-            if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-                (void)hipEventDestroy(e0);
-                (void)hipEventDestroy(e1);
-                return fail(MK_EDEVICE, "autotune timing failed");
-            }
+            MK_HIP(hipEventSynchronize(e1), "autotune sync");
+            MK_HIP(hipEventElapsedTime(&ms, e0, e1), "autotune timing");
             if (ms_out) ms_out[which * kNumShapes + v] = ms / kReps;
             if (ms < best[which]) {
                 best[which] = ms;
                 pick[which] = v;
             }
         }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     MK_HIP(hipGetLastError(), "autotune launch");
     ctx->dev.tuned_tiles[GT] = {pick[0], pick[1]};
+    return MK_OK;
+}
+
+// Average time of `steps` CMux steps of party k-1 on `count` gates run as
+// `parts` sub-batches (abar all zero: the shifts do not change the work).
+static int time_steps(mk_ctx *ctx, size_t count, int parts, const uint32_t *abar, hipStream_t s,
+                      hipEvent_t e0, hipEvent_t e1, float *ms) {
+    const mk_params &P = ctx->p;
+    Split sp{1, {count, 0}, {0, 0}};
+    if (parts == 2) {
+        const size_t GT = (count + 31) / 32;
+        sp = Split{2, {(GT + 1) / 2 * 32, 0}, {0, (GT + 1) / 2 * 32}};
+        sp.cnt[1] = count - sp.cnt[0];
+    }
+    MfmaArgs a[2];
+    int rc = prepare(ctx, abar, sp, s, a);
+    if (rc) return rc;
+    hipStream_t ss[2];
+    const int st0 = (P.k - 1) * P.n, nsteps = std::min(8, P.n);
+    for (int rep = 0; rep < 2; ++rep) {  // first pass warms up
+        MK_HIP(hipEventRecord(e0, s), "autotune record");
+        if ((rc = fork_parts(ctx, sp.parts, s, ss)) || (rc = enqueue_steps(ctx, a, sp.parts, ss, st0, st0 + nsteps)) ||
+            (rc = join_parts(ctx, sp.parts, s, ss)))
+            return rc;
+        MK_HIP(hipEventRecord(e1, s), "autotune record");
+        MK_HIP(hipEventSynchronize(e1), "autotune sync");
+    }
+    MK_HIP(hipEventElapsedTime(ms, e0, e1), "autotune timing");
+    *ms /= nsteps;
+    return MK_OK;
+}
+
+// Tile shapes for `count` gates and for its half, then whether a batch of
+// `count` runs faster whole or as two sub-batches on two streams.
+int autotune(mk_ctx *ctx, size_t count, hipStream_t s, int *v1_out, int *v2_out, float *ms_out) {
+    const mk_params &P = ctx->p;
+    DeviceKeys &D = ctx->dev;
+    hipEvent_t e0, e1;
+    MK_HIP(hipEventCreate(&e0), "autotune event");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(MK_EDEVICE, "autotune event");
+    }
+    const int saved_prof = D.profiling;
+    D.profiling = 0;
+    int pick[2], pick_half[2];
+    int rc = tune_shapes(ctx, count, s, e0, e1, pick, ms_out);
+    const size_t GT = (count + 31) / 32;
+    uint32_t *abar = nullptr;
+    float whole = 0, split = 0;
+    if (!rc && GT >= 2) {
+        const size_t half = (GT + 1) / 2 * 32;
+        rc = tune_shapes(ctx, half, s, e0, e1, pick_half, nullptr);
+        const size_t words = count * ((size_t)P.k * P.n + 1);
+        if (!rc && hipMalloc((void **)&abar, words * 4) != hipSuccess) {
+            abar = nullptr;
+            rc = fail(MK_ENOMEM, "autotune: device allocation failed");
+        }
+        if (!rc && hipMemsetAsync(abar, 0, words * 4, s) != hipSuccess) rc = fail(MK_EDEVICE, "autotune memset");
+        if (!rc) rc = time_steps(ctx, count, 1, abar, s, e0, e1, &whole);
+        if (!rc) rc = time_steps(ctx, count, 2, abar, s, e0, e1, &split);
+        if (!rc) D.tuned_parts[(int)GT] = split < whole ? 2 : 1;
+    }
+    if (abar) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(abar);
+    }
+    D.profiling = saved_prof;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
     if (v1_out) *v1_out = pick[0];
     if (v2_out) *v2_out = pick[1];
     return MK_OK;
@@ -1074,6 +1222,20 @@ int mk_set_tiles(mk_ctx *ctx, int gemm1_shape, int gemm2_shape) {
         return fail(MK_EINVAL, "mk_set_tiles: shape does not divide N/32");
     ctx->dev.force_tiles[0] = gemm1_shape;
     ctx->dev.force_tiles[1] = gemm2_shape;
+    return MK_OK;
+}
+
+int mk_set_split(mk_ctx *ctx, size_t count, int parts) {
+    if (!ctx || !count || parts < 0 || parts > 2) return fail(MK_EINVAL, "mk_set_split: bad argument");
+    const int GT = (int)((count + 31) / 32);
+    if (parts == 0) ctx->dev.tuned_parts.erase(GT);
+    else ctx->dev.tuned_parts[GT] = parts;
+    return MK_OK;
+}
+
+int mk_get_split(const mk_ctx *ctx, size_t count, int32_t *parts) {
+    if (!ctx || !parts) return fail(MK_EINVAL, "mk_get_split: bad argument");
+    *parts = split_for(ctx, count).parts;
     return MK_OK;
 }
 

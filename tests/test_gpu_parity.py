@@ -230,6 +230,40 @@ def test_every_tile_shape_is_bit_identical(torch_cuda, shape):
     assert np.array_equal(outs[0], outs[1])
 
 
+def test_split_batches_are_bit_identical(torch_cuda):
+    """A batch run as two sub-batches on two streams gives the same words as
+    the whole batch and as the oracle (ragged halves: 70 gates -> 64 + 6)."""
+    K, ctx = helpers.gpu_world("C1")
+    types, m1, m2 = mi.gate_batch(70, seed=15)
+    c1, c2 = _workload(K, types, m1, m2, seed=150)
+    ref = helpers.oracle_gates("C1", types, c1, c2)
+    outs = []
+    for parts in (2, 1):
+        ctx.set_split(70, parts)
+        assert ctx.get_split(70) == parts
+        try:
+            outs.append(_gates_on_gpu(torch_cuda, ctx, types, c1, c2, 1))
+        finally:
+            ctx.set_split(70, 0)
+    assert np.array_equal(outs[0], ref) and np.array_equal(outs[1], ref)
+    K2, ctx2 = helpers.gpu_world("C2")
+    P = K2.params
+    abar = np.random.default_rng(19).integers(0, 2 * P.N, (300, P.lwe_words)).astype(np.uint32)
+    d = torch_cuda.device("cuda:0")
+    ta = torch_cuda.from_numpy(abar.view(np.int32)).to(d)
+    accs = []
+    for parts in (1, 2):
+        acc = torch_cuda.zeros((300, (P.k + 1) * P.N), dtype=torch_cuda.int32, device=d)
+        ctx2.set_split(300, parts)
+        try:
+            ctx2.blind_rotate(ta, acc, max_steps=600, path=1)
+        finally:
+            ctx2.set_split(300, 0)
+        torch_cuda.cuda.synchronize()
+        accs.append(acc.cpu().numpy())
+    assert np.array_equal(accs[0], accs[1])
+
+
 def test_smallest_ring_shapes(torch_cuda):
     """N = 128 (4 K-blocks): the 256-row shapes are refused, the default is
     the first shape that fits, and every admissible shape matches the

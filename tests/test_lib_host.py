@@ -113,6 +113,15 @@ def test_tile_shape_arguments():
     assert ctx.get_tiles(1000) == (0, 0)
     with pytest.raises(mk.MkError):
         ctx.set_tiles(5, 0)
+    assert ctx.get_split(1000) == 1
+    ctx.set_split(1000, 2)
+    assert ctx.get_split(1000) == 2 and ctx.get_split(1024) == 2 and ctx.get_split(900) == 1
+    ctx.set_split(1000, 0)
+    assert ctx.get_split(1000) == 1
+    assert ctx.get_split(20) == 1
+    for bad in (-1, 3):
+        with pytest.raises(mk.MkError):
+            ctx.set_split(1000, bad)
     small = mk.Context(helpers.lib_params(OP.C1S), 3)   # N/32 = 4: 256-row shapes refused
     assert small.get_tiles(1000) == (1, 1)
     with pytest.raises(mk.MkError):
