@@ -78,6 +78,9 @@ __global__ void diag_tiles_kernel(const uint32_t *__restrict__ ext, int N, size_
     reinterpret_cast<uint4 *>(out)[idx] = make_uint4(w[0], w[1], w[2], w[3]);
 }
 
+struct MfmaArgs;
+__global__ void mfma_rotdec_kernel(MfmaArgs a, int step);
+
 int mfma_upload(mk_ctx *ctx, const std::vector<uint32_t> &evk, hipStream_t s) {
     (void)evk;
     const mk_params &P = ctx->p;
@@ -95,6 +98,12 @@ int mfma_upload(mk_ctx *ctx, const std::vector<uint32_t> &evk, hipStream_t s) {
         D.evk_win = nullptr;
         return fail(MK_ENOMEM, "device allocation failed: MFMA evaluation-key tiles");
     }
+    // rotdec keeps 8 accumulator rows in LDS (128 KB at N = 4096)
+    const int rows_lds = 8 * P.N * 4;
+    if (rows_lds > 65536)
+        MK_HIP(hipFuncSetAttribute((const void *)mfma_rotdec_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   rows_lds),
+               "rotdec LDS attribute");
     // the extended plain-path keys are already queued for upload on `s`
     const size_t per_poly = (size_t)4 * ND * 64;
     const size_t chunk = (size_t)1 << 20;  // polys per launch bound
@@ -144,102 +153,105 @@ __global__ void mfma_init_kernel(MfmaArgs a) {
     a.acc[idx] = v;
 }
 
-// Digit kernels.  A workgroup of 256 threads (4 waves) owns one 32-gate tile
-// and a range of kDigKB K-blocks (32 kDigKB coefficients).  Phase 1: wave w
-// handles gates w, w+4, .., w+28 and lane L the coefficients m0 + L + 64 q,
-// so every load instruction reads 64 consecutive words of one gate's row and
-// all 8 gates' loads are in flight together; the ell digit bytes go to LDS
-// as [l][gate][coefficient] (rows padded by 16 bytes against bank
-// conflicts).  Phase 2 writes whole 1 KB MFMA B fragments (lane L = 32 h +
-// gate, 16 bytes = coefficients 32 kb + 16 h ..).
-constexpr int kDigKB = 4;
-constexpr int kDigCoef = 32 * kDigKB;          // coefficients per workgroup
-constexpr int kDigRow = kDigCoef + 16;          // padded LDS row (bytes)
-constexpr int kDigQ = kDigCoef / 64;            // coefficients per lane per gate
+// Digit kernels.  Fragment piece (slot or V, l, gate tile, K-block kb, lane
+// L = 32 h + g) is the 16 bytes of digit l of coefficients 32 kb + 16 h ..
+// + 15 of gate 32 gt + g: one thread computes one piece for all ell digits
+// from 16 consecutive coefficients and writes ell 16-byte stores, so a wave
+// writes whole 1 KB fragments (wdec) or 128-byte runs of them (rotdec).
+constexpr int kMaxEll = 3;   // ell * 8 <= 30
 
-__device__ __forceinline__ void digits_to_lds(int8_t *lds, int ell, int g, int mm, uint32_t y) {
-    for (int l = 0; l < ell; ++l)
-        lds[(l * 32 + g) * kDigRow + mm] = (int8_t)((int)((y >> (24 - 8 * l)) & 255u) - 128);
-}
-
-__device__ __forceinline__ void lds_to_frags(const int8_t *lds, int ell, int8_t *dst_l0,
-                                             size_t l_stride, int kb0) {
-    // fragment (l, kb) lives at dst_l0 + l * l_stride + kb * 1024
-    const int tid = threadIdx.x;
-    const int nfr = ell * kDigKB;
-    for (int f = tid / 64; f < nfr; f += 4) {
-        const int l = f / kDigKB, kk = f % kDigKB;
-        const int L = tid & 63, g = L & 31, h = L >> 5;
-        const uint4 v = *reinterpret_cast<const uint4 *>(lds + (l * 32 + g) * kDigRow + 32 * kk + 16 * h);
-        *reinterpret_cast<uint4 *>(dst_l0 + l * l_stride + (size_t)(kb0 + kk) * kTileBytes + L * 16) = v;
+__device__ __forceinline__ void put_digits(int8_t *dst_l0, size_t l_stride, int ell, const uint32_t (&y)[16]) {
+    // digit l of y = byte (3 - l) of y (the offset folds in rounding and
+    // the +128 bias), minus 128
+#pragma unroll
+    for (int l = 0; l < kMaxEll; ++l) {
+        if (l >= ell) break;
+        uint32_t w[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            uint32_t v = 0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                v |= ((((y[4 * q + b] >> (24 - 8 * l)) & 255u) - 128u) & 255u) << (8 * b);
+            w[q] = v;
+        }
+        *reinterpret_cast<uint4 *>(dst_l0 + l * l_stride) = make_uint4(w[0], w[1], w[2], w[3]);
     }
 }
 
-// rotdec: item (j, gate tile, K-block group); P_j = X^-a ACC_j - ACC_j.
+// rotdec: workgroup = (slot j, 8 consecutive gates).  The 8 rows ACC_j are
+// read once, with 16-byte loads, into LDS; then every piece takes its 16
+// plain and 16 rotated coefficients from there: P_j = X^-a ACC_j - ACC_j,
+// (X^-a c)[m] = c[m + a] for m + a < N and -c[m + a - N] beyond.
 __global__ __launch_bounds__(256) void mfma_rotdec_kernel(MfmaArgs a, int step) {
-    __shared__ __align__(16) int8_t lds[3 * 32 * kDigRow];  // ell <= 3 (ell*8 <= 30)
-    const int N = a.N, K1 = a.k + 1, NB = N / 32, GT = a.GP / 32, KG = NB / kDigKB;
-    int item = blockIdx.x;
-    const int kg = item % KG;
-    item /= KG;
-    const int gt = item % GT;
-    const int j = item / GT;
-    const int m0 = kg * kDigCoef;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int stride = a.k * a.n + 1;
-    uint32_t y[8][kDigQ];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const int g = wave + 4 * i, gg = gt * 32 + g;
-        const int shift = gg < a.G ? (int)a.abar[(size_t)gg * stride + 1 + step] : 0;
-        const uint32_t *row = a.acc + ((size_t)gg * K1 + j) * N;
-#pragma unroll
-        for (int q = 0; q < kDigQ; ++q) {
-            const int m = m0 + lane + 64 * q;
-            const int s = m + shift;
-            const uint32_t src = row[s & (N - 1)];
-            const uint32_t rot = ((s >> a.log2N) & 1) ? 0u - src : src;
-            y[i][q] = rot - row[m] + a.offset;
+    extern __shared__ __align__(16) uint32_t rows[];   // [8][N]
+    const int N = a.N, K1 = a.k + 1, NB = N / 32, GT = a.GP / 32;
+    const int groups = a.GP / 8;
+    const int j = blockIdx.x / groups, g8 = blockIdx.x % groups;
+    const int tid = threadIdx.x;
+    {
+        const int per_row = N / 4;  // uint4 per row
+        for (int v = tid; v < 8 * per_row; v += 256) {
+            const int gi = v / per_row, c4 = v % per_row;
+            const size_t gate = (size_t)g8 * 8 + gi;
+            reinterpret_cast<uint4 *>(rows)[v] =
+                reinterpret_cast<const uint4 *>(a.acc + (gate * K1 + j) * N)[c4];
         }
     }
-#pragma unroll
-    for (int i = 0; i < 8; ++i)
-#pragma unroll
-        for (int q = 0; q < kDigQ; ++q) digits_to_lds(lds, a.ell, wave + 4 * i, lane + 64 * q, y[i][q]);
+    const int gi = tid % 8;
+    const int gate = g8 * 8 + gi;
+    const int stride = a.k * a.n + 1;
+    const int shift = gate < a.G ? (int)a.abar[(size_t)gate * stride + 1 + step] : 0;
     __syncthreads();
-    lds_to_frags(lds, a.ell, a.U + ((size_t)j * a.ell * GT + gt) * NB * kTileBytes,
-                 (size_t)GT * NB * kTileBytes, kg * kDigKB);
+    const uint32_t *row = rows + gi * N;
+    const int gt = gate / 32, L0 = gate % 32;
+    const size_t l_stride = (size_t)GT * NB * kTileBytes;
+    int8_t *base = a.U + ((size_t)j * a.ell * GT + gt) * NB * kTileBytes;
+    for (int item = tid / 8; item < NB * 2; item += 32) {  // item = (kb, h)
+        const int kb = item / 2, h = item % 2;
+        const int m0 = 32 * kb + 16 * h;
+        uint32_t y[16];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint4 p = *reinterpret_cast<const uint4 *>(row + m0 + 4 * q);
+            const uint32_t pv[4] = {p.x, p.y, p.z, p.w};
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int s = m0 + 4 * q + b + shift;
+                const uint32_t src = row[s & (N - 1)];
+                const uint32_t rot = ((s >> a.log2N) & 1) ? 0u - src : src;
+                y[4 * q + b] = rot - pv[b] + a.offset;
+            }
+        }
+        put_digits(base + (size_t)kb * kTileBytes + (32 * h + L0) * 16, l_stride, a.ell, y);
+    }
 }
 
-// wdec: item (gate tile, K-block group); V = g^-1(sum_j W_j).
+// wdec: one thread per V fragment piece; V = g^-1(sum_j W_j) over the live
+// partial rows (16-byte loads: a wave reads 32 gates x 128 bytes).
 __global__ __launch_bounds__(256) void mfma_wdec_kernel(MfmaArgs a, int live) {
-    __shared__ __align__(16) int8_t lds[3 * 32 * kDigRow];
-    const int N = a.N, NB = N / 32, GT = a.GP / 32, KG = NB / kDigKB;
-    const int kg = blockIdx.x % KG;
-    const int gt = blockIdx.x / KG;
-    const int m0 = kg * kDigCoef;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    uint32_t y[8][kDigQ];
+    const int N = a.N, NB = N / 32, GT = a.GP / 32;
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (size_t)GT * NB * 64) return;
+    const int L = (int)(idx % 64), kb = (int)((idx / 64) % NB), gt = (int)(idx / (64 * (size_t)NB));
+    const int g = L % 32, h = L / 32;
+    const size_t gate = (size_t)gt * 32 + g;
+    const int m0 = 32 * kb + 16 * h;
+    uint32_t y[16];
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
+    for (int e = 0; e < 16; ++e) y[e] = a.offset;
+    for (int jj = 0; jj < live; ++jj) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(a.W + ((size_t)jj * a.GP + gate) * N + m0);
 #pragma unroll
-        for (int q = 0; q < kDigQ; ++q) y[i][q] = a.offset;
-    for (int j = 0; j < live; ++j) {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int gg = gt * 32 + wave + 4 * i;
-            const uint32_t *row = a.W + ((size_t)j * a.GP + gg) * N + m0 + lane;
-#pragma unroll
-            for (int q = 0; q < kDigQ; ++q) y[i][q] += row[64 * q];
+        for (int q = 0; q < 4; ++q) {
+            const uint4 v = src[q];
+            y[4 * q + 0] += v.x;
+            y[4 * q + 1] += v.y;
+            y[4 * q + 2] += v.z;
+            y[4 * q + 3] += v.w;
         }
     }
-#pragma unroll
-    for (int i = 0; i < 8; ++i)
-#pragma unroll
-        for (int q = 0; q < kDigQ; ++q) digits_to_lds(lds, a.ell, wave + 4 * i, lane + 64 * q, y[i][q]);
-    __syncthreads();
-    lds_to_frags(lds, a.ell, a.V + (size_t)gt * NB * kTileBytes, (size_t)GT * NB * kTileBytes,
-                 kg * kDigKB);
+    put_digits(a.V + ((size_t)gt * NB + kb) * kTileBytes + L * 16, (size_t)GT * NB * kTileBytes, a.ell, y);
 }
 
 // ------------------------------------------------------------- GEMMs ----
@@ -912,7 +924,7 @@ static Split split_for(const mk_ctx *ctx, size_t count) {
 // kernel arguments (part i: gates off[i] .. off[i] + cnt[i] - 1).
 static int prepare(mk_ctx *ctx, const uint32_t *abar, const Split &sp, hipStream_t s, MfmaArgs *a) {
     const mk_params &P = ctx->p;
-    if (P.N < kDigCoef) return fail(MK_EPARAM, "int8-MFMA path needs N >= 128");
+    if (P.N < 128) return fail(MK_EPARAM, "int8-MFMA path needs N >= 128");
     const int K1 = P.k + 1, N = P.N, ell = P.bk_ell;
     size_t need = 0;
     for (int i = 0; i < sp.parts; ++i) {
@@ -981,7 +993,8 @@ static void shapes_for(const mk_ctx *ctx, int GT, int &v1, int &v2) {
 // Enqueues CMux steps st0 .. st1-1 of every part, part i on stream ss[i].
 static int enqueue_steps(mk_ctx *ctx, const MfmaArgs *a, int parts, hipStream_t *ss, int st0, int st1) {
     const mk_params &P = ctx->p;
-    const int K1 = P.k + 1, NB = P.N / 32, KG = NB / kDigKB;
+    const int K1 = P.k + 1, NB = P.N / 32;
+    const size_t rows_lds = (size_t)8 * P.N * 4;   // rotdec: 8 accumulator rows
     int GT[2], v1[2], v2[2];
     for (int i = 0; i < parts; ++i) {
         GT[i] = a[i].GP / 32;
@@ -998,8 +1011,8 @@ static int enqueue_steps(mk_ctx *ctx, const MfmaArgs *a, int parts, hipStream_t 
             hipStream_t s = ss[i];
             {
                 StageTimer t6(ctx, 6, s);
-                hipLaunchKernelGGL(mfma_rotdec_kernel, dim3((unsigned)(live * GT[i] * KG)), dim3(256), 0, s,
-                                   a[i], st);
+                hipLaunchKernelGGL(mfma_rotdec_kernel, dim3((unsigned)(live * GT[i] * 4)), dim3(256), rows_lds,
+                                   s, a[i], st);
             }
             {
                 StageTimer t4(ctx, 4, s);
@@ -1007,8 +1020,8 @@ static int enqueue_steps(mk_ctx *ctx, const MfmaArgs *a, int parts, hipStream_t 
             }
             {
                 StageTimer t7(ctx, 7, s);
-                hipLaunchKernelGGL(mfma_wdec_kernel, dim3((unsigned)(GT[i] * KG)), dim3(256), 0, s, a[i],
-                                   live);
+                hipLaunchKernelGGL(mfma_wdec_kernel, dim3((unsigned)(GT[i] * NB / 4)), dim3(256), 0, s,
+                                   a[i], live);
             }
             {
                 StageTimer t5(ctx, 5, s);
