@@ -111,6 +111,43 @@ def cpu_baseline(gates_per_core: int):
 
 
 # ---------------------------------------------------------------- GPU ----
+def operator_rate(torch, mk, ctx, pairs):
+    """16-bit two's-complement adder (5k gates per pair, Alg. 3) on `pairs`
+    operand pairs, captured as one HIP graph; the timed launch follows one
+    warm-up launch, and every sum is decrypted and checked."""
+    bits = 16
+    circ = mk.build_operator(mk.OP_ADD, bits)
+    levels, live, width, _ = mk.circuit_stats(circ)
+    a, b = mi.operand_pairs(pairs, bits, seed=4)
+    words = C2["k"] * C2["n"] + 1
+    cols = np.concatenate([mi.to_bits(a, bits).T, mi.to_bits(b, bits).T])
+    in_ct = np.stack([ctx.encrypt(0 if i < bits else 1, col, seed=400 + i) for i, col in enumerate(cols)])
+    dev = torch.device("cuda:0")
+    inp = torch.from_numpy(np.ascontiguousarray(in_ct).view(np.int32)).to(dev)
+    out = torch.zeros((bits, pairs, words), dtype=torch.int32, device=dev)
+    for cnt in sorted({pairs, 2 * pairs, width * pairs}):   # the levels' batch sizes
+        ctx.autotune(cnt)
+    print("bench: operator autotune done; capturing the add16 graph", file=sys.stderr, flush=True)
+    g = ctx.circuit_graph(circ, inp, out)
+    try:
+        print("bench: graph of %d pieces captured; launching" % g.info()[2], file=sys.stderr, flush=True)
+        g.launch()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.launch()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    finally:
+        g.close()
+    dec = np.stack([ctx.decrypt(x) for x in out.cpu().numpy().view(np.uint32)])
+    v = mi.from_bits(dec.T)
+    want = ((a + b + (1 << (bits - 1))) & ((1 << bits) - 1)) - (1 << (bits - 1))
+    assert np.array_equal(v, want), "adder outputs do not decrypt to the sums"
+    return {"operator": "add16", "pairs": pairs, "levels": levels, "gates_per_pair": live,
+            "seconds": dt, "operators_per_s": pairs / dt, "gates_per_s": pairs * live / dt,
+            "graph": True}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,6 +156,8 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--path", choices=["mfma", "i32"], default="mfma")
     ap.add_argument("--cpu-gates-per-core", type=int, default=1)
+    ap.add_argument("--operator-pairs", type=int, default=1024,
+                    help="operand pairs of the 16-bit adder timed through a HIP graph (0: skip)")
     ap.add_argument("--tiles", default="", metavar="G1,G2",
                     help="force the two GEMM tile shapes instead of autotuning")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -226,6 +265,8 @@ def main():
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                                 "copy-calibrated)",
                 "kernel": kname, "avg_launch_ms": g1_ms,
+                "hbm_GBs": (measured_traffic(kname) / (g1_ms * 1e-3) / 1e9
+                            if measured_traffic(kname) else None),
                 "launches": ln[4],
                 "whole_rotation_tops": 8 * macs / (br_ms * 1e-3) / 1e12}
     else:
@@ -233,6 +274,7 @@ def main():
         roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_TORUS_MACS / 1e12,
                 "unit": "T Torus32-MAC/s", "frac": achieved / PEAK_VALU_TORUS_MACS, "traffic": None,
                 "kernel": "br_plain_kernel", "avg_launch_ms": br_ms}
+    print("bench: headline measured", file=sys.stderr, flush=True)
     res = {
         "metric": "bootstrapped MK gates/sec on 1 MI355X (int8-MFMA batched vs int32 plain), bit-exact",
         "value": value, "unit": "gates/s", "n_gpus": 1, "steps": args.steps,
@@ -250,6 +292,8 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    if head == mk.PATH_MFMA_I8 and args.operator_pairs > 0:
+        res["operators"] = operator_rate(torch, mk, ctx, args.operator_pairs)
     if head == mk.PATH_MFMA_I8 and "i32" in outs and args.plain_steps > 0:
         psec, pms, pln = timed(mk.PATH_I32, args.plain_steps, 0, level=1)
         res["plain_i32"] = {"value": BATCH / psec, "ms_per_step": psec * 1e3,

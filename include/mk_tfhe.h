@@ -192,19 +192,23 @@ int mk_eval_circuit(mk_ctx *ctx, const mk_circuit *c, const uint32_t *in_dev,
  * of the path, so later calls on the context cannot move them) and
  * captures, on a stream of its own, the evaluation reading in_dev and
  * writing out_dev (layouts as in mk_eval_circuit); in_dev and out_dev must
- * stay valid for the graph's lifetime.  Each mk_graph_launch on `stream`
- * then evaluates the circuit on the current contents of in_dev (the
- * evaluation key must stay uploaded).  Launches of one graph must not
- * overlap (they share its buffers).  mk_graph_info reports the number of
- * levels and of bootstrapped gates per launch; mk_graph_destroy waits for
- * the device and frees everything.  Errors: those of mk_eval_circuit, plus
+ * stay valid for the graph's lifetime.  The capture is cut into consecutive
+ * pieces of about 1024 kernels (256 CMux steps), since a single graph of a
+ * whole operator (thousands of kernels per level) is beyond what graph
+ * instantiation handles.  Each mk_graph_launch on `stream` replays the
+ * pieces in order and so evaluates the circuit on the current contents of
+ * in_dev (the evaluation key must stay uploaded).  Launches of one graph
+ * must not overlap (they share its buffers).  mk_graph_info reports the
+ * number of levels, of bootstrapped gates per launch and of pieces (any
+ * pointer may be NULL); mk_graph_destroy waits for the device and frees
+ * everything.  Errors: those of mk_eval_circuit, plus
  * MK_EDEVICE when capture or instantiation fails. */
 typedef struct mk_graph mk_graph;
 int mk_circuit_graph_create(mk_ctx *ctx, const mk_circuit *c, const uint32_t *in_dev,
                             uint32_t *out_dev, size_t batch, size_t stride, int path,
                             mk_graph **graph);
 int mk_graph_launch(mk_graph *graph, void *stream);
-int mk_graph_info(const mk_graph *graph, int32_t *n_levels, int64_t *gates);
+int mk_graph_info(const mk_graph *graph, int32_t *n_levels, int64_t *gates, int32_t *pieces);
 int mk_graph_destroy(mk_graph *graph);
 
 /* Host-side analysis of a netlist as mk_eval_circuit levels it: number of

@@ -64,7 +64,8 @@ _SIGS = {
     "mk_circuit_graph_create": ([_vp, ctypes.POINTER(MkCircuit), _vp, _vp, _sz, _sz, _i,
                                  ctypes.POINTER(_vp)], _i),
     "mk_graph_launch": ([_vp, _vp], _i),
-    "mk_graph_info": ([_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)], _i),
+    "mk_graph_info": ([_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
+                       ctypes.POINTER(ctypes.c_int32)], _i),
     "mk_graph_destroy": ([_vp], _i),
     "mk_blind_rotate": ([_vp, _vp, _vp, _sz, _i, _i, _vp], _i),
     "mk_extract_keyswitch": ([_vp, _vp, _vp, _sz, _sz, _i, _vp], _i),
@@ -289,9 +290,10 @@ class Graph:
         _check(_L.mk_graph_launch(self._h, _stream(stream)))
 
     def info(self):
-        lv, g = ctypes.c_int32(), ctypes.c_int64()
-        _check(_L.mk_graph_info(self._h, ctypes.byref(lv), ctypes.byref(g)))
-        return lv.value, g.value
+        """(levels, bootstrapped gates per launch, graph pieces)."""
+        lv, g, pc = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32()
+        _check(_L.mk_graph_info(self._h, ctypes.byref(lv), ctypes.byref(g), ctypes.byref(pc)))
+        return lv.value, g.value, pc.value
 
     def close(self):
         if getattr(self, "_h", None):

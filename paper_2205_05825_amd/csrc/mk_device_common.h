@@ -41,6 +41,9 @@ size_t ks_scratch_need(const mk_params &P, size_t count);
 int ks_mfma_upload(mk_ctx *ctx, hipStream_t s);
 int launch_ks_mfma(mk_ctx *ctx, const uint32_t *acc, uint32_t *out, size_t count, size_t stride,
                    hipStream_t s);
+// During a graph capture: ends the current graph after enough kernels and
+// begins the next one on the same stream (mk_engine.hip).
+int capture_checkpoint(mk_ctx *ctx, hipStream_t s, int kernels);
 // Sample extraction + key switching on the given path (mk_device.hip).
 int run_key_switch(mk_ctx *ctx, const uint32_t *acc, uint32_t *out, size_t count, size_t stride, int path,
                    hipStream_t s);

@@ -28,8 +28,9 @@
 // scratch) so that later calls on the context cannot move it.
 struct mk_graph {
     mk_ctx *ctx = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    // consecutive pieces of the captured sequence, replayed in order
+    std::vector<hipGraph_t> graphs;
+    std::vector<hipGraphExec_t> execs;
     void *buf[4] = {nullptr, nullptr, nullptr, nullptr};
     size_t bytes[4] = {0, 0, 0, 0};
     int levels = 0;
@@ -432,9 +433,40 @@ int enqueue_run(mk_ctx *ctx, const CircuitRun &R, uint32_t *gate_scratch, const 
     return MK_OK;
 }
 
+// A capture is cut into consecutive graphs of about kGraphKernels kernel
+// nodes (one rotation step is 4): each piece stays far from the node counts
+// at which building one graph for a whole operator failed (one level of a
+// 2-party Table 7 rotation alone is 4480 kernels), and pieces replayed in
+// order on one stream are equivalent to the whole sequence.
+constexpr int kGraphKernels = 1024;
+
+struct CaptureState {
+    mk_graph *g;
+    int kernels;
+};
+
+int capture_checkpoint(mk_ctx *ctx, hipStream_t s, int kernels) {
+    CaptureState *cs = (CaptureState *)ctx->dev.capture;
+    if (!cs) return MK_OK;
+    cs->kernels += kernels;
+    if (cs->kernels < kGraphKernels) return MK_OK;
+    hipGraph_t piece = nullptr;
+    if (hipStreamEndCapture(s, &piece) != hipSuccess || !piece)
+        return fail(MK_EDEVICE, "graph capture: ending a piece failed");
+    cs->g->graphs.push_back(piece);
+    cs->kernels = 0;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail(MK_EDEVICE, "graph capture: starting a piece failed");
+    return MK_OK;
+}
+
 void graph_release(mk_graph *g) {
-    if (g->exec) (void)hipGraphExecDestroy(g->exec);
-    if (g->graph) (void)hipGraphDestroy(g->graph);
+    for (hipGraphExec_t e : g->execs)
+        if (e) (void)hipGraphExecDestroy(e);
+    for (hipGraph_t gr : g->graphs)
+        if (gr) (void)hipGraphDestroy(gr);
+    g->execs.clear();
+    g->graphs.clear();
     bool any = false;
     for (void *p : g->buf) any |= p != nullptr;
     if (any) (void)hipDeviceSynchronize();
@@ -442,8 +474,6 @@ void graph_release(mk_graph *g) {
         if (p) (void)hipFree(p);
         p = nullptr;
     }
-    g->exec = nullptr;
-    g->graph = nullptr;
 }
 
 }  // namespace mk
@@ -542,41 +572,52 @@ int mk_circuit_graph_create(mk_ctx *ctx, const mk_circuit *c, const uint32_t *in
     D.mfma_scratch = g->buf[2]; D.mfma_scratch_bytes = g->bytes[2];
     D.ks_scratch = g->buf[3]; D.ks_scratch_bytes = g->bytes[3];
     D.profiling = 0;
-    hipGraph_t graph_raw = nullptr;
+    CaptureState state{g, 0};
+    D.capture = &state;
     rc = MK_OK;
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         rc = fail(MK_EDEVICE, "mk_circuit_graph_create: capture failed to start");
     } else {
         rc = enqueue_run(ctx, R, (uint32_t *)g->buf[1], in_dev, out_dev, cs);
-        const hipError_t e = hipStreamEndCapture(cs, &graph_raw);
-        if (!rc && e != hipSuccess) rc = fail(MK_EDEVICE, "mk_circuit_graph_create: capture failed");
+        // end whatever capture is open (also after an error inside a piece)
+        hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(cs, &st) == hipSuccess && st != hipStreamCaptureStatusNone) {
+            hipGraph_t piece = nullptr;
+            const hipError_t e = hipStreamEndCapture(cs, &piece);
+            if (piece) g->graphs.push_back(piece);
+            if (!rc && e != hipSuccess) rc = fail(MK_EDEVICE, "mk_circuit_graph_create: capture failed");
+        }
     }
+    D.capture = nullptr;
     D.scratch = save_p[0]; D.scratch_bytes = save_b[0];
     D.mfma_scratch = save_p[1]; D.mfma_scratch_bytes = save_b[1];
     D.ks_scratch = save_p[2]; D.ks_scratch_bytes = save_b[2];
     D.profiling = save_prof;
     (void)hipStreamDestroy(cs);
-    g->graph = graph_raw;
     if (rc) return abandon(rc);
-    if (hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess) {
-        g->exec = nullptr;
-        return abandon(fail(MK_EDEVICE, "mk_circuit_graph_create: instantiation failed"));
+    for (hipGraph_t piece : g->graphs) {
+        hipGraphExec_t e = nullptr;
+        if (hipGraphInstantiate(&e, piece, nullptr, nullptr, 0) != hipSuccess)
+            return abandon(fail(MK_EDEVICE, "mk_circuit_graph_create: instantiation failed"));
+        g->execs.push_back(e);
     }
     *graph = g;
     return MK_OK;
 }
 
 int mk_graph_launch(mk_graph *g, void *stream) {
-    if (!g || !g->exec) return fail(MK_EINVAL, "mk_graph_launch: null graph");
-    if (hipGraphLaunch(g->exec, (hipStream_t)stream) != hipSuccess)
-        return fail(MK_EDEVICE, "mk_graph_launch: launch failed");
+    if (!g || g->execs.empty()) return fail(MK_EINVAL, "mk_graph_launch: null graph");
+    for (hipGraphExec_t e : g->execs)
+        if (hipGraphLaunch(e, (hipStream_t)stream) != hipSuccess)
+            return fail(MK_EDEVICE, "mk_graph_launch: launch failed");
     return MK_OK;
 }
 
-int mk_graph_info(const mk_graph *g, int32_t *n_levels, int64_t *gates) {
+int mk_graph_info(const mk_graph *g, int32_t *n_levels, int64_t *gates, int32_t *pieces) {
     if (!g) return fail(MK_EINVAL, "mk_graph_info: null graph");
     if (n_levels) *n_levels = g->levels;
     if (gates) *gates = g->gates;
+    if (pieces) *pieces = (int32_t)g->execs.size();
     return MK_OK;
 }
 

@@ -62,6 +62,9 @@ struct DeviceKeys {
     // Sub-batches of the MFMA rotation (1 or 2, run on aux streams), tuned
     // per batch size in 32-gate tiles; streams and events made on first use.
     std::map<int, int> tuned_parts;
+    // Graph capture in progress (mk_circuit_graph_create): the capture is cut
+    // into consecutive graphs of at most about kGraphSteps CMux steps.
+    void *capture = nullptr;
     void *aux_stream[2] = {nullptr, nullptr};
     void *aux_event[3] = {nullptr, nullptr, nullptr};
 };

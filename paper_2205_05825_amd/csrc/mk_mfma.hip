@@ -1028,6 +1028,10 @@ static int enqueue_steps(mk_ctx *ctx, const MfmaArgs *a, int parts, hipStream_t 
                 gemm2(v2[i], a[i], party, bit, GT[i], NB, s);
             }
         }
+        if (ctx->dev.capture) {
+            int rc = capture_checkpoint(ctx, ss[0], 4 * parts);
+            if (rc) return rc;
+        }
     }
     MK_HIP(hipGetLastError(), "mfma step launch");
     return MK_OK;

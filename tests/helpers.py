@@ -117,3 +117,53 @@ def encrypt_operands(K, values, bits, party, seed):
     import mk_inputs as mi
     cols = mi.to_bits(values, bits).T
     return np.stack([tfhe.encrypt(K, party, col, seed=seed + 1000 * i) for i, col in enumerate(cols)])
+
+
+def sampled_level_parity(name, circ, in_ct, evaluate, samples, seed, workers=8):
+    """Per-gate parity inside a full-size circuit run.
+
+    `samples` (gate, instance) items are drawn (seeded) from the bootstrapped
+    gates; the circuit is evaluated on the GPU with those gates' input and
+    output wires appended to its outputs (evaluate(circuit) -> u32[n_out, B,
+    words]); then the oracle recomputes each sampled gate from the GPU's own
+    input ciphertexts (constants as trivial ciphertexts, inputs as given) and
+    the result must equal the GPU's output word for word.  By induction over
+    the levels this checks every level at these shapes.  Returns the GPU
+    outputs of the original circuit's outputs."""
+    from concurrent.futures import ThreadPoolExecutor
+    import paper_2205_05825_amd as mk
+    K = oracle_keys(name)
+    P = K.params
+    W = P.lwe_words
+    rng = np.random.default_rng(seed)
+    boot = [i for i, g in enumerate(circ.gates) if g[0] != mk.NOT]
+    picks = [(int(rng.choice(boot)), int(rng.integers(0, in_ct.shape[1]))) for _ in range(samples)]
+    extra = []
+    for gi, _ in picks:
+        _, a, b, o = (int(x) for x in circ.gates[gi])
+        extra += [a, b, o]
+    n0 = len(circ.outputs)
+    ext = mk.Circuit(circ.n_wires, circ.inputs, np.concatenate([circ.outputs, np.array(extra, np.int32)]),
+                     circ.gates)
+    got = evaluate(ext)
+    input_pos = {int(w): i for i, w in enumerate(circ.inputs)}
+    evk = K.evaluation_key()
+
+    def wire_ct(w, row, inst):
+        if w in (0, 1):
+            return tfhe.trivial(P, [w])[0]
+        if w in input_pos:
+            return np.asarray(in_ct[input_pos[w], inst, :W], np.uint32)
+        return got[row, inst, :W]
+
+    def check(k):
+        gi, inst = picks[k]
+        t, a, b, _ = (int(x) for x in circ.gates[gi])
+        base = n0 + 3 * k
+        c1, c2 = wire_ct(a, base, inst), wire_ct(b, base + 1, inst)
+        return np.array_equal(tfhe.bootstrapped_gate(K, t, c1, c2, evk), got[base + 2, inst, :W])
+
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        ok = list(ex.map(check, range(len(picks))))
+    assert all(ok), [p for p, f in zip(picks, ok) if not f]
+    return got[:n0]

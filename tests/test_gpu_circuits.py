@@ -126,8 +126,10 @@ def test_graph_replays_match_eager(torch_cuda, path):
     out = torch_cuda.full((len(circ.outputs), batch, W), -1, dtype=torch_cuda.int32, device=d)
     g = ctx.circuit_graph(circ, inp, out, path=path)
     try:
-        levels, gates = g.info()
+        levels, gates, pieces = g.info()
         assert levels >= 1 and gates == batch * mk.circuit_stats(circ)[1]
+        if path == 1:   # 4 kernels per CMux step, k*n = 128 steps per level
+            assert pieces >= levels * 4 * 128 // 1024
         rng = np.random.default_rng(70 + path)
         for rep in range(3):
             a = rng.integers(-8, 8, batch)
@@ -146,3 +148,33 @@ def test_graph_replays_match_eager(torch_cuda, path):
             assert np.array_equal(mi.from_bits(dec.T), _wrap(a + b, k)), rep
     finally:
         g.close()
+
+
+def test_graph_of_a_table7_operator(torch_cuda):
+    """A 16-bit adder at the 2-party Table 7 shape captured as a graph (about
+    4500 kernels per level, cut into bounded pieces): two launches equal the
+    eager evaluation word for word and decrypt to the sums."""
+    import paper_2205_05825_amd as mk
+    K, ctx = helpers.gpu_world("C2")
+    k, batch = 16, 6
+    circ = mk.build_operator(mk.OP_ADD, k)
+    a, b = mi.operand_pairs(batch, k, seed=8)
+    in_ct = np.concatenate([helpers.encrypt_operands(K, a, k, 0, 800),
+                            helpers.encrypt_operands(K, b, k, 1, 810)])
+    d = torch_cuda.device("cuda:0")
+    inp = torch_cuda.from_numpy(np.ascontiguousarray(in_ct).view(np.int32)).to(d)
+    out = torch_cuda.zeros((k, batch, in_ct.shape[2]), dtype=torch_cuda.int32, device=d)
+    g = ctx.circuit_graph(circ, inp, out, path=1)
+    try:
+        levels, _, pieces = g.info()
+        assert pieces >= levels * 4 * K.params.k * K.params.n // 1024
+        eager = _eval(torch_cuda, ctx, circ, in_ct, 1)
+        for _ in range(2):
+            out.fill_(0)
+            g.launch()
+            torch_cuda.cuda.synchronize()
+            assert np.array_equal(out.cpu().numpy().view(np.uint32), eager)
+    finally:
+        g.close()
+    dec = np.stack([tfhe.decrypt(K, o) for o in eager])
+    assert np.array_equal(mi.from_bits(dec.T), _wrap(a + b, k))

@@ -28,7 +28,7 @@ def _enc_operand(ctx, values, bits, party, seed):
     return np.stack([ctx.encrypt(party, col, seed=seed + 1000 * i) for i, col in enumerate(cols)])
 
 
-def _run(torch, ctx, circ, in_ct, path=1):
+def _words(torch, ctx, circ, in_ct, path=1):
     d = torch.device("cuda:0")
     inp = torch.from_numpy(np.ascontiguousarray(in_ct).view(np.int32)).to(d)
     out = torch.zeros((len(circ.outputs), in_ct.shape[1], in_ct.shape[2]), dtype=torch.int32, device=d)
@@ -36,7 +36,11 @@ def _run(torch, ctx, circ, in_ct, path=1):
     ctx.eval_circuit(circ, inp, out, path=path)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    o = out.cpu().numpy().view(np.uint32)
+    return out.cpu().numpy().view(np.uint32), dt
+
+
+def _run(torch, ctx, circ, in_ct, path=1):
+    o, dt = _words(torch, ctx, circ, in_ct, path)
     return np.stack([ctx.decrypt(x) for x in o]), dt
 
 
@@ -93,9 +97,17 @@ def test_c4_operators_subset(torch_cuda, op):
     circ = mk.build_operator(code, 16)
     a, b = mi.operand_pairs(32, 16, seed=4, nonzero_second=True)
     in_ct = np.concatenate([_enc_operand(ctx, a, 16, 0, 5), _enc_operand(ctx, b, 16, 1, 6)])
-    dec, dt = _run(torch_cuda, ctx, circ, in_ct)
+    timing = {}
+
+    def evaluate(c):
+        words, timing["dt"] = _words(torch_cuda, ctx, c, in_ct)
+        return words
+
+    # six sampled (gate, pair) items recomputed by the oracle from the GPU's inputs
+    outs = helpers.sampled_level_parity("C2", circ, in_ct, evaluate, 6, seed=40 + code)
+    dec = np.stack([ctx.decrypt(x) for x in outs])
     _, live, _, _ = mk.circuit_stats(circ)
-    print("C4 16-bit %s: 32 pairs, %d gates/pair, %.2f s, %.0f gates/s" % (op, live, dt, live * 32 / dt))
+    print("C4 16-bit %s: 32 pairs, %d gates/pair, %.2f s" % (op, live, timing["dt"]))
     v = mi.from_bits(dec.T)
     if op == "add":
         assert np.array_equal(v, _wrap(a + b, 16))
@@ -107,3 +119,35 @@ def test_c4_operators_subset(torch_cuda, op):
         q = np.abs(a) // np.abs(b) * np.sign(a) * np.sign(b)
         assert np.array_equal(mi.from_bits(dec[:16].T), _wrap(q, 16))
         assert np.array_equal(mi.from_bits(dec[16:].T), _wrap(a - q * b, 16))
+
+
+def test_c5_lr_step_full(torch_cuda):
+    """Config 5: one encrypted gradient-descent step on m=64 samples, d=4
+    features split between the two parties, 16-bit Q8.8 values, learning rate
+    2^-6 as an arithmetic shift; the new weights decrypt to the integer
+    replica's, and sampled gates match the oracle word for word."""
+    import paper_2205_05825_amd as mk
+    from oracle import lr
+    K, ctx = helpers.gpu_world("C2")
+    m, d = 64, 4
+    X, y, w_true = mi.lr_data(m, d, seed=5)
+    w = np.clip(np.rint(w_true * 256 * 0.5), -32768, 32767).astype(np.int64)   # a starting point
+    circ = mk.build_lr_step(m, d)
+    bits = lr.input_bits(X, y, w)[:, 0]
+    owner = lr.input_owner(m, d)
+    in_ct = np.zeros((len(bits), 1, K.params.lwe_words), np.uint32)
+    for p in (0, 1):
+        sel = np.nonzero(owner == p)[0]
+        in_ct[sel, 0] = ctx.encrypt(p, bits[sel], seed=900 + p)
+    timing = {}
+
+    def evaluate(c):
+        words, timing["dt"] = _words(torch_cuda, ctx, c, in_ct)
+        return words
+
+    outs = helpers.sampled_level_parity("C2", circ, in_ct, evaluate, 6, seed=55)
+    dec = np.stack([ctx.decrypt(x) for x in outs])[:, 0]
+    levels, live, width, _ = mk.circuit_stats(circ)
+    print("C5 LR step: %d levels, %d gates, widest level %d, %.1f s, %.0f gates/s"
+          % (levels, live, width, timing["dt"], live / timing["dt"]))
+    assert np.array_equal(mi.from_bits(dec.reshape(d, 16)), lr.replica_step(X, y, w))
