@@ -148,6 +148,53 @@ def operator_rate(torch, mk, ctx, pairs):
             "graph": True}
 
 
+def naive_comparison(torch, mk, ctx, batch):
+    """Table 2 on one MI355X: every gate type run as the scheme's single
+    bootstrapped gate (NOT: the free linear NOT) and as its NAND-only
+    composition, on the same `batch` input pairs; the second of two runs is
+    timed, and every output is decrypted against the truth table."""
+    dev = torch.device("cuda:0")
+    _, m1, m2 = mi.gate_batch(batch, seed=6)
+    c1, c2 = ctx.encrypt(0, m1, seed=600), ctx.encrypt(1, m2, seed=601)
+    ta = torch.from_numpy(c1.view(np.int32)).to(dev)
+    tb = torch.from_numpy(c2.view(np.int32)).to(dev)
+    inp = torch.stack([ta, tb])
+    res = {}
+    names = {mk.NAND: "NAND", mk.AND: "AND", mk.OR: "OR", mk.NOR: "NOR", mk.XOR: "XOR", mk.XNOR: "XNOR",
+             mk.NOT: "NOT"}
+    for t, name in names.items():
+        want = 1 - m1 if t == mk.NOT else np.array([mi.plain_gate(t, int(x), int(y)) for x, y in zip(m1, m2)])
+        out = torch.zeros_like(ta)
+        types = torch.full((batch,), t, dtype=torch.uint8, device=dev)
+
+        def scheme():
+            if t == mk.NOT:
+                ctx.lwe_not(ta, out)
+            else:
+                ctx.bootstrap_gate(types, ta, tb, out)
+
+        circ = mk.build_naive_gate(t)
+        nout = torch.zeros((1, batch, ta.shape[1]), dtype=torch.int32, device=dev)
+
+        def naive():
+            ctx.eval_circuit(circ, inp, nout)
+
+        times = []
+        for fn, o in ((scheme, out), (naive, nout[0])):
+            for rep in range(2):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                fn()
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+            assert np.array_equal(ctx.decrypt(o.cpu().numpy().view(np.uint32)), want), name
+            times.append(dt)
+        levels, gates, _, _ = mk.circuit_stats(circ)
+        res[name] = {"scheme_ms": times[0] * 1e3, "nand_composed_ms": times[1] * 1e3,
+                     "nand_gates": gates, "nand_depth": levels, "speedup": times[1] / times[0]}
+    return {"pairs": batch, "gates": res}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,6 +205,8 @@ def main():
     ap.add_argument("--cpu-gates-per-core", type=int, default=1)
     ap.add_argument("--operator-pairs", type=int, default=1024,
                     help="operand pairs of the 16-bit adder timed through a HIP graph (0: skip)")
+    ap.add_argument("--naive-pairs", type=int, default=1024,
+                    help="input pairs of the scheme-vs-NAND-composed gate comparison (0: skip)")
     ap.add_argument("--tiles", default="", metavar="G1,G2",
                     help="force the two GEMM tile shapes instead of autotuning")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -294,6 +343,10 @@ def main():
     }
     if head == mk.PATH_MFMA_I8 and args.operator_pairs > 0:
         res["operators"] = operator_rate(torch, mk, ctx, args.operator_pairs)
+        print("bench: operators measured", file=sys.stderr, flush=True)
+    if head == mk.PATH_MFMA_I8 and args.naive_pairs > 0:
+        res["naive_nand_gates"] = naive_comparison(torch, mk, ctx, args.naive_pairs)
+        print("bench: NAND-composed gates measured", file=sys.stderr, flush=True)
     if head == mk.PATH_MFMA_I8 and "i32" in outs and args.plain_steps > 0:
         psec, pms, pln = timed(mk.PATH_I32, args.plain_steps, 0, level=1)
         res["plain_i32"] = {"value": BATCH / psec, "ms_per_step": psec * 1e3,

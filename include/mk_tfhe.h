@@ -261,6 +261,12 @@ int mk_build_operator(int op, int kbits, mk_gate *gates, int32_t *n_gates,
  * sums mod 2^16.  Inputs: x (m*d values row-major), y (m), w (d), 16 bits
  * each LSB first; outputs: w' (d values).  Sizing as mk_build_operator.
  * Errors: MK_EINVAL (m*d > 4096, shift > 15). */
+/* The comparison design of Table 2 (left column): gate `type` (NAND..XNOR,
+ * or MK_GATE_NOT) built from bootstrapped NAND gates only, NOT included
+ * (NOT a = NAND(a, a)); inputs a, b (b unused by NOT), one output.  Same
+ * two-call convention as mk_build_operator.  Errors: MK_EINVAL. */
+int mk_build_naive_gate(int type, mk_gate *gates, int32_t *n_gates, int32_t *n_wires,
+                        int32_t *inputs, int32_t *outputs);
 int mk_build_lr_step(int m, int d, int shift, mk_gate *gates, int32_t *n_gates,
                      int32_t *n_wires, int32_t *inputs, int32_t *outputs);
 

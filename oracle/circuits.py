@@ -269,6 +269,47 @@ def divider(k: int, dividend_bits: int | None = None) -> Netlist:
 
 # ----------------------------------------------------------- evaluation ----
 
+def naive_gate(t: int) -> Netlist:
+    """The comparison design of Table 2 (left column): every gate built from
+    bootstrapped NAND gates only, NOT included (NOT a = NAND(a, a)).  Inputs
+    a, b (b unused by NOT); one output.  Depths: NAND and NOT 1, AND and OR
+    2, NOR and XOR 3, XNOR 4."""
+    nl = Netlist(fold=False)
+    a, b = nl.input(), nl.input()
+
+    def nand(x, y):
+        return nl._new(NAND, x, y)
+
+    def naive_or(x, y):
+        return nand(nand(x, x), nand(y, y))
+
+    def naive_xor(x, y):
+        n = nand(x, y)
+        return nand(nand(x, n), nand(y, n))
+
+    if t == NAND:
+        out = nand(a, b)
+    elif t == AND:
+        n = nand(a, b)
+        out = nand(n, n)
+    elif t == OR:
+        out = naive_or(a, b)
+    elif t == NOR:
+        o = naive_or(a, b)
+        out = nand(o, o)
+    elif t == XOR:
+        out = naive_xor(a, b)
+    elif t == XNOR:
+        x = naive_xor(a, b)
+        out = nand(x, x)
+    elif t == NOT:
+        out = nand(a, a)
+    else:
+        raise ValueError("gate type")
+    nl.outputs = [out]
+    return nl
+
+
 def eval_plain(nl: Netlist, in_bits) -> np.ndarray:
     """Evaluate on plaintext bits, vectorised over instances.
     in_bits: u8[n_inputs, B]; returns u8[n_outputs, B]."""

@@ -72,6 +72,9 @@ _SIGS = {
     "mk_build_operator": ([_i, _i, ctypes.POINTER(MkGate), ctypes.POINTER(ctypes.c_int32),
                            ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                            ctypes.POINTER(ctypes.c_int32)], _i),
+    "mk_build_naive_gate": ([_i, ctypes.POINTER(MkGate), ctypes.POINTER(ctypes.c_int32),
+                             ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                             ctypes.POINTER(ctypes.c_int32)], _i),
     "mk_build_lr_step": ([_i, _i, _i, ctypes.POINTER(MkGate), ctypes.POINTER(ctypes.c_int32),
                           ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                           ctypes.POINTER(ctypes.c_int32)], _i),
@@ -343,6 +346,12 @@ def build_operator(op: int, kbits: int) -> "Circuit":
     n_in = {OP_DIV2: 3 * kbits}.get(op, 2 * kbits)
     n_out = {OP_ADD: kbits, OP_SUB: kbits}.get(op, 2 * kbits)
     return _netlist(lambda *a: _L.mk_build_operator(op, kbits, *a), n_in, n_out)
+
+
+def build_naive_gate(gate_type: int) -> "Circuit":
+    """Gate `gate_type` made of bootstrapped NAND gates only (Table 2's
+    comparison design)."""
+    return _netlist(lambda *a: _L.mk_build_naive_gate(gate_type, *a), 2, 1)
 
 
 def build_lr_step(m: int, d: int, shift: int = 12) -> "Circuit":

@@ -261,6 +261,51 @@ int mk_build_operator(int op, int kbits, mk_gate *gates, int32_t *n_gates, int32
     return export_netlist(b, gates, n_gates, n_wires, inputs, outputs);
 }
 
+int mk_build_naive_gate(int type, mk_gate *gates, int32_t *n_gates, int32_t *n_wires, int32_t *inputs,
+                        int32_t *outputs) {
+    if (!n_gates || !n_wires) return fail(MK_EINVAL, "mk_build_naive_gate: null count pointer");
+    if (type < 0 || type > MK_GATE_NOT) return fail(MK_EINVAL, "mk_build_naive_gate: unknown gate type");
+    Builder b(false);  // no folding: NAND(x, x) stays a bootstrapped gate
+    std::vector<int> in = inputs_n(b, 2);
+    const int x = in[0], y = in[1];
+    auto nand = [&](int u, int v) { return b.g(MK_GATE_NAND, u, v); };
+    auto naive_or = [&](int u, int v) {
+        const int nu = nand(u, u);  // sequenced: the gate order is the netlist
+        const int nv = nand(v, v);
+        return nand(nu, nv);
+    };
+    auto naive_xor = [&](int u, int v) {
+        const int n = nand(u, v);
+        const int p = nand(u, n);
+        const int q = nand(v, n);
+        return nand(p, q);
+    };
+    int out;
+    switch (type) {
+        case MK_GATE_NAND: out = nand(x, y); break;
+        case MK_GATE_AND: {
+            const int n = nand(x, y);
+            out = nand(n, n);
+            break;
+        }
+        case MK_GATE_OR: out = naive_or(x, y); break;
+        case MK_GATE_NOR: {
+            const int o = naive_or(x, y);
+            out = nand(o, o);
+            break;
+        }
+        case MK_GATE_XOR: out = naive_xor(x, y); break;
+        case MK_GATE_XNOR: {
+            const int z = naive_xor(x, y);
+            out = nand(z, z);
+            break;
+        }
+        default: out = nand(x, x); break;  // NOT
+    }
+    b.outputs = {out};
+    return export_netlist(b, gates, n_gates, n_wires, inputs, outputs);
+}
+
 int mk_build_lr_step(int m, int d, int shift, mk_gate *gates, int32_t *n_gates, int32_t *n_wires,
                      int32_t *inputs, int32_t *outputs) {
     if (!n_gates || !n_wires) return fail(MK_EINVAL, "mk_build_lr_step: null count pointer");

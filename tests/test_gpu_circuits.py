@@ -178,3 +178,20 @@ def test_graph_of_a_table7_operator(torch_cuda):
         g.close()
     dec = np.stack([tfhe.decrypt(K, o) for o in eager])
     assert np.array_equal(mi.from_bits(dec.T), _wrap(a + b, k))
+
+
+@pytest.mark.parametrize("t", range(7))
+def test_naive_gates_parity(torch_cuda, t):
+    """NAND-composed gates (Table 2's comparison design) through the engine:
+    every output word equals the oracle's gate-by-gate evaluation, and the
+    outputs decrypt to the truth table."""
+    import paper_2205_05825_amd as mk
+    K, ctx = helpers.gpu_world("C1B")
+    circ = mk.build_naive_gate(t)
+    a = np.array([0, 0, 1, 1, 1, 0], np.uint8)
+    b = np.array([0, 1, 0, 1, 1, 1], np.uint8)
+    in_ct = np.stack([tfhe.encrypt(K, 0, a, seed=60 + t), tfhe.encrypt(K, 1, b, seed=70 + t)])
+    got = _eval(torch_cuda, ctx, circ, in_ct, 1)
+    assert np.array_equal(got, helpers.oracle_circuit("C1B", C.naive_gate(t), in_ct))
+    want = [1 - x for x in a] if t == mk.NOT else [mi.plain_gate(t, int(x), int(y)) for x, y in zip(a, b)]
+    assert tfhe.decrypt(K, got[0]).tolist() == want

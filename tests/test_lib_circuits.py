@@ -33,6 +33,12 @@ def test_lr_netlist_matches_oracle(m, d):
     _same(mk.build_lr_step(m, d), lr.build_netlist(m, d))
 
 
+@pytest.mark.parametrize("t", range(7))
+def test_naive_gate_netlists_match_oracle(t):
+    import paper_2205_05825_amd as mk
+    _same(mk.build_naive_gate(t), C.naive_gate(t))
+
+
 def test_circuit_stats():
     import paper_2205_05825_amd as mk
     add = mk.build_operator(mk.OP_ADD, 8)

@@ -160,3 +160,25 @@ def test_encrypted_operators_exhaustive_toy(op, k):
     outs = C.eval_encrypted(nl, K, np.concatenate([ca, cb]))
     dec = np.stack([tfhe.decrypt(K, o) for o in outs])
     assert np.array_equal(dec, _run(nl, k, a, b))
+
+
+@pytest.mark.parametrize("t", [C.NAND, C.AND, C.OR, C.NOR, C.XOR, C.XNOR, C.NOT])
+def test_naive_nand_gates(t):
+    """Table 2's comparison design: every gate from bootstrapped NANDs only.
+    Truth tables on all inputs (plain and encrypted at the toy shape); only
+    NAND gates; the depths 1/2/2/3/3/4/1 that make its times multiples of one
+    bootstrap."""
+    nl = C.naive_gate(t)
+    assert all(g[0] == C.NAND for g in nl.gates)
+    a = np.array([0, 0, 1, 1], np.uint8)
+    b = np.array([0, 1, 0, 1], np.uint8)
+    want = [1 - x for x in a] if t == C.NOT else [mi.plain_gate(t, int(x), int(y)) for x, y in zip(a, b)]
+    assert C.eval_plain(nl, np.stack([a, b]))[0].tolist() == want
+    depth = {}
+    for typ, x, y, o in nl.gates:
+        depth[o] = 1 + max(depth.get(x, 0), depth.get(y, 0))
+    assert depth[nl.outputs[0]] == {C.NAND: 1, C.AND: 2, C.OR: 2, C.NOR: 3, C.XOR: 3, C.XNOR: 4, C.NOT: 1}[t]
+    K = tfhe.generate(OP.TOY, 32)
+    ct = np.stack([tfhe.encrypt(K, 0, a, seed=40), tfhe.encrypt(K, 1, b, seed=41)])
+    outs = C.eval_encrypted(nl, K, ct)
+    assert tfhe.decrypt(K, outs[0]).tolist() == want
