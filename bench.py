@@ -47,7 +47,8 @@ MFMA_SOURCE = os.path.join(ROOT, "paper_2205_05825_amd", "csrc", "mk_mfma.hip")
 # mk_mfma.hip), as rocprofv3 names the kernel.
 GEMM1_KERNEL = {0: "mfma_gemm1_limb_kernel<8, 1, 2>", 1: "mfma_gemm1_limb_kernel<4, 2, 2>",
                 2: "mfma_gemm1_limb_kernel<4, 1, 3>", 3: "mfma_gemm1_kernel<2, 1, 2>",
-                4: "mfma_gemm1_limb_kernel<8, 2, 1>"}
+                4: "mfma_gemm1_limb_kernel<8, 2, 1>", 5: "mfma_gemm1_split_kernel<2, 1>",
+                6: "mfma_gemm1_split_kernel<1, 1>", 7: "mfma_gemm1_split_kernel<1, 2>"}
 
 
 def measured_traffic(kernel):
@@ -148,6 +149,41 @@ def operator_rate(torch, mk, ctx, pairs):
             "graph": True}
 
 
+def formula_lr(torch, mk, ctx, sets, m=64, frac=8):
+    """Closed-form one-feature regression (§3.4 Eqs. (2)-(3), Alg. 7) on
+    `sets` data sets of m pairs of 8-bit integers, pair i encrypted by party
+    i mod 2, evaluated level by level in one eager call.  Every slope and
+    intercept is decrypted and checked against float least squares within
+    the rounding bound of the integer formula: m (1 + |w|) / sum (x - x̄)^2
+    + 2^-frac for the slope, that times |x̄| plus 2^-frac for the intercept."""
+    circ = mk.build_lr_formula(m, frac)
+    levels, live, width, _ = mk.circuit_stats(circ)
+    x, y, _, _ = mi.formula_lr_data(sets, m, seed=5)
+    vals = np.concatenate([x, y], axis=1)                         # [sets, 2m]
+    bits = mi.to_bits(vals.ravel(), 8).reshape(sets, -1).T       # [16m, sets]
+    owner = np.repeat(np.array([i % 2 for i in range(m)] * 2), 8)
+    in_ct = np.stack([ctx.encrypt(int(owner[i]), bits[i], seed=800 + i) for i in range(len(bits))])
+    dev = torch.device("cuda:0")
+    inp = torch.from_numpy(np.ascontiguousarray(in_ct).view(np.int32)).to(dev)
+    out = torch.zeros((32, sets, in_ct.shape[2]), dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.eval_circuit(circ, inp, out)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    dec = np.stack([ctx.decrypt(o) for o in out.cpu().numpy().view(np.uint32)])
+    slope, icpt = mi.from_bits(dec[:16].T) / 2.0 ** frac, mi.from_bits(dec[16:].T) / 2.0 ** frac
+    f = 2.0 ** -frac
+    for s in range(sets):
+        A = np.vstack([x[s].astype(float), np.ones(m)]).T
+        w, c = np.linalg.lstsq(A, y[s].astype(float), rcond=None)[0]
+        tol = m * (1 + abs(w)) / ((x[s] - x[s].mean()) ** 2).sum() + f
+        assert abs(slope[s] - w) <= tol and abs(icpt[s] - c) <= tol * abs(x[s].mean()) + f, \
+            "closed-form regression output %d off the least-squares fit" % s
+    return {"sets": sets, "m": m, "levels": levels, "gates_per_set": live, "widest_level": width,
+            "seconds": dt, "gates_per_s": sets * live / dt, "ms_per_level": dt * 1e3 / levels}
+
+
 def naive_comparison(torch, mk, ctx, batch):
     """Table 2 on one MI355X: every gate type run as the scheme's single
     bootstrapped gate (NOT: the free linear NOT) and as its NAND-only
@@ -205,6 +241,8 @@ def main():
     ap.add_argument("--cpu-gates-per-core", type=int, default=1)
     ap.add_argument("--operator-pairs", type=int, default=1024,
                     help="operand pairs of the 16-bit adder timed through a HIP graph (0: skip)")
+    ap.add_argument("--formula-sets", type=int, default=0,
+                    help="data sets of the closed-form regression run (m = 64 pairs each; 0: skip)")
     ap.add_argument("--naive-pairs", type=int, default=1024,
                     help="input pairs of the scheme-vs-NAND-composed gate comparison (0: skip)")
     ap.add_argument("--tiles", default="", metavar="G1,G2",
@@ -344,6 +382,9 @@ def main():
     if head == mk.PATH_MFMA_I8 and args.operator_pairs > 0:
         res["operators"] = operator_rate(torch, mk, ctx, args.operator_pairs)
         print("bench: operators measured", file=sys.stderr, flush=True)
+    if head == mk.PATH_MFMA_I8 and args.formula_sets > 0:
+        res["lr_formula"] = formula_lr(torch, mk, ctx, args.formula_sets)
+        print("bench: closed-form regression measured", file=sys.stderr, flush=True)
     if head == mk.PATH_MFMA_I8 and args.naive_pairs > 0:
         res["naive_nand_gates"] = naive_comparison(torch, mk, ctx, args.naive_pairs)
         print("bench: NAND-composed gates measured", file=sys.stderr, flush=True)

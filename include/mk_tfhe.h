@@ -261,14 +261,32 @@ int mk_build_operator(int op, int kbits, mk_gate *gates, int32_t *n_gates,
  * sums mod 2^16.  Inputs: x (m*d values row-major), y (m), w (d), 16 bits
  * each LSB first; outputs: w' (d values).  Sizing as mk_build_operator.
  * Errors: MK_EINVAL (m*d > 4096, shift > 15). */
+int mk_build_lr_step(int m, int d, int shift, mk_gate *gates, int32_t *n_gates,
+                     int32_t *n_wires, int32_t *inputs, int32_t *outputs);
+
+/* Closed-form one-feature linear regression (§3.4 Eqs. (2)-(3), Alg. 7) on
+ * m pairs of signed 8-bit integers.  Sums are taken mod 2^16 and divisions
+ * truncate toward zero (the divider array of MK_OP_DIV/DIV2):
+ *   S_x = sum x_i, S_y = sum y_i; xbar = S_x / m, ybar = S_y / m (low 8 bits);
+ *   dx_i = x_i - xbar, dy_i = y_i - ybar (mod 2^8);
+ *   num = sum dy_i dx_i, den = sum dx_i dx_i (8 x 8 -> 16-bit products);
+ *   slope = (num 2^frac) / den (32-bit dividend);
+ *   intercept = (S_y 2^frac - slope S_x) / m (32-bit dividend, 16x16 product).
+ * The centred sums equal Eq. (2)'s numerator and denominator in exact
+ * arithmetic and keep the rounding of xbar, ybar small.  Inputs: x_0..x_{m-1}
+ * then y_0..y_{m-1}, 8 bits each LSB first; outputs: slope then intercept,
+ * 16 bits each, both with `frac` fractional bits.  The constant m enters as
+ * constant wires.  Sizing as mk_build_operator.  Errors: MK_EINVAL (m outside
+ * [1, 4096], frac outside [0, 15]). */
+int mk_build_lr_formula(int m, int frac, mk_gate *gates, int32_t *n_gates, int32_t *n_wires,
+                        int32_t *inputs, int32_t *outputs);
+
 /* The comparison design of Table 2 (left column): gate `type` (NAND..XNOR,
  * or MK_GATE_NOT) built from bootstrapped NAND gates only, NOT included
  * (NOT a = NAND(a, a)); inputs a, b (b unused by NOT), one output.  Same
  * two-call convention as mk_build_operator.  Errors: MK_EINVAL. */
 int mk_build_naive_gate(int type, mk_gate *gates, int32_t *n_gates, int32_t *n_wires,
                         int32_t *inputs, int32_t *outputs);
-int mk_build_lr_step(int m, int d, int shift, mk_gate *gates, int32_t *n_gates,
-                     int32_t *n_wires, int32_t *inputs, int32_t *outputs);
 
 /* Kernel timing.  With level 1, every pipeline stage is bracketed by HIP
  * events recorded on the caller's stream; level 2 also brackets each kernel
@@ -286,9 +304,14 @@ int mk_get_profile(mk_ctx *ctx, double *ms, int64_t *launches, int reset);
  * shapes, where a workgroup's four waves hold the four key limbs of one
  * output block: 0 = 256 rows x 32 gates, 1 = 128 rows x 64 gates, 2 = 128
  * rows x 32 gates, 4 = 256 rows x 64 gates; shape 3 = one wave per 64 rows
- * x 32 gates with all four limbs.  Results are identical for every shape;
- * only speed differs.  Without tuning the first shape whose row count
- * divides N is used.
+ * x 32 gates with all four limbs; K-split shapes 5 (64 rows), 6 (32 rows)
+ * and 7 (32 rows, each key polynomial's K range in two halves) x 32 gates,
+ * where each of the workgroup's waves takes one part of the contraction
+ * and their sums are added in LDS (short chains for small batches).
+ * Results are identical for every shape; only speed differs.  Without
+ * tuning a batch of GT 32-gate tiles uses gemm1 shape 6 (GT <= 2), 5
+ * (GT <= 4), 3 (GT <= 12), else the first shape whose row count divides N;
+ * gemm2 shape 6 (GT <= 4), 5 (GT <= 12), else 3.
  *   mk_autotune   times every shape of both kernels on the scratch buffers of
  *                 a batch of `count` gates (synchronous on `stream`) and
  *                 records the fastest for that batch size; ms (optional,
@@ -307,7 +330,7 @@ int mk_get_profile(mk_ctx *ctx, double *ms, int64_t *launches, int reset);
  *                 at profiling level 2 and while `stream` is being captured
  *                 into a graph; results are identical either way.
  * Errors: MK_EINVAL, MK_ESTATE (key not uploaded), MK_ENOMEM, MK_EDEVICE. */
-#define MK_TILE_SHAPES 5
+#define MK_TILE_SHAPES 8
 int mk_autotune(mk_ctx *ctx, size_t count, void *stream, int32_t *gemm1_shape,
                 int32_t *gemm2_shape, float *ms);
 int mk_set_tiles(mk_ctx *ctx, int gemm1_shape, int gemm2_shape);

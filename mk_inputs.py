@@ -114,3 +114,17 @@ def lr_data(m: int, d: int, seed: int, frac_bits: int = 8, noise_std=0.1):
     scale = float(1 << frac_bits)
     q = lambda v: np.clip(np.rint(v * scale), -32768, 32767).astype(np.int64)
     return q(X), q(y), w
+
+
+def formula_lr_data(sets: int, m: int, seed: int, noise_std=2.0):
+    """``sets`` independent one-feature data sets of ``m`` integer pairs for
+    the closed-form regression: x uniform in [-16, 15], slope a ~ U[-3, 3],
+    intercept c ~ U[-20, 20], y = round(a x + c + noise), noise ~
+    N(0, noise_std^2), saturated to int8.  Returns (x int64[sets, m],
+    y int64[sets, m], a float[sets], c float[sets])."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x = rng.integers(-16, 16, size=(sets, m), dtype=np.int64)
+    a = rng.uniform(-3.0, 3.0, size=sets)
+    c = rng.uniform(-20.0, 20.0, size=sets)
+    y = a[:, None] * x + c[:, None] + rng.normal(0.0, noise_std, size=(sets, m))
+    return x, np.clip(np.rint(y), -128, 127).astype(np.int64), a, c

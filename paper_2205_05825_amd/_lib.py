@@ -26,7 +26,7 @@ _L = ctypes.CDLL(LIB_PATH)
 
 MK_OK, MK_EINVAL, MK_ENOMEM, MK_EDEVICE, MK_ESTATE, MK_EPARAM = 0, -1, -2, -3, -4, -5
 PATH_I32, PATH_MFMA_I8 = 0, 1
-TILE_SHAPES = 5
+TILE_SHAPES = 8
 NAND, AND, OR, NOR, XOR, XNOR, NOT = 0, 1, 2, 3, 4, 5, 6
 
 
@@ -78,6 +78,9 @@ _SIGS = {
     "mk_build_lr_step": ([_i, _i, _i, ctypes.POINTER(MkGate), ctypes.POINTER(ctypes.c_int32),
                           ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                           ctypes.POINTER(ctypes.c_int32)], _i),
+    "mk_build_lr_formula": ([_i, _i, ctypes.POINTER(MkGate), ctypes.POINTER(ctypes.c_int32),
+                             ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                             ctypes.POINTER(ctypes.c_int32)], _i),
     "mk_circuit_stats": ([ctypes.POINTER(MkCircuit), ctypes.POINTER(ctypes.c_int32),
                           ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
                           ctypes.POINTER(ctypes.c_int32)], _i),
@@ -357,6 +360,13 @@ def build_naive_gate(gate_type: int) -> "Circuit":
 def build_lr_step(m: int, d: int, shift: int = 12) -> "Circuit":
     """Netlist of one fixed-point gradient-descent step (16-bit values)."""
     return _netlist(lambda *a: _L.mk_build_lr_step(m, d, shift, *a), 16 * (m * d + m + d), 16 * d)
+
+
+def build_lr_formula(m: int, frac: int = 8) -> "Circuit":
+    """Netlist of the closed-form one-feature regression on m pairs of 8-bit
+    integers: outputs the slope and the intercept, 16 bits each with `frac`
+    fractional bits."""
+    return _netlist(lambda *a: _L.mk_build_lr_formula(m, frac, *a), 16 * m, 32)
 
 
 def circuit_stats(c: "Circuit"):

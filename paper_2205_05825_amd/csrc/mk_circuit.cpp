@@ -1,6 +1,7 @@
 // Netlist builders of the k-bit two's-complement operators (§3.3, §4.3-4.5,
-// Algs. 3-6) and of one fixed-point gradient-descent step of linear
-// regression (§4.6).
+// Algs. 3-6), of one fixed-point gradient-descent step of linear regression
+// (§4.6), of the closed-form regression (§3.4 Eqs. (2)-(3), Alg. 7) and of
+// Table 2's NAND-only gates.
 //
 // Wire 0 / wire 1 are the constants 0 / 1, inputs come next, every gate adds
 // one wire.  Adder: ripple of one-bit adders x = a^b, s = x^c,
@@ -342,6 +343,63 @@ int mk_build_lr_step(int m, int d, int shift, mk_gate *gates, int32_t *n_gates, 
         std::vector<int> nw = sub(w[j], step);
         b.outputs.insert(b.outputs.end(), nw.begin(), nw.end());
     }
+    return export_netlist(b, gates, n_gates, n_wires, inputs, outputs);
+}
+
+int mk_build_lr_formula(int m, int frac, mk_gate *gates, int32_t *n_gates, int32_t *n_wires,
+                        int32_t *inputs, int32_t *outputs) {
+    if (!n_gates || !n_wires) return fail(MK_EINVAL, "mk_build_lr_formula: null count pointer");
+    if (m < 1 || m > 4096 || frac < 0 || frac > 15)
+        return fail(MK_EINVAL, "mk_build_lr_formula: size out of range");
+    constexpr int kIn = 8, kW = 16;
+    Builder b(true);
+    std::vector<std::vector<int>> x(m), y(m);
+    for (int i = 0; i < m; ++i) x[i] = inputs_n(b, kIn);
+    for (int i = 0; i < m; ++i) y[i] = inputs_n(b, kIn);
+    std::vector<int> cm(kW);
+    for (int t = 0; t < kW; ++t) cm[t] = (m >> t) & 1 ? kOne : kZero;
+    // v sign-extended to `bits`, optionally times 2^frac (wiring only)
+    auto widen = [&](const std::vector<int> &v, int bits, int shift) {
+        std::vector<int> o(shift, kZero);
+        o.insert(o.end(), v.begin(), v.end());
+        o.resize(bits, v.back());
+        return o;
+    };
+    auto sub = [&](const std::vector<int> &u, const std::vector<int> &v) {
+        std::vector<int> nv(v.size());
+        for (size_t i = 0; i < v.size(); ++i) nv[i] = b.g(MK_GATE_XOR, v[i], kOne);
+        return b.ripple(u, nv, kOne);
+    };
+    auto total = [&](const std::vector<std::vector<int>> &terms) {
+        std::vector<int> acc = terms[0];
+        for (size_t i = 1; i < terms.size(); ++i) acc = b.ripple(acc, terms[i], kZero);
+        return acc;
+    };
+    auto quotient = [&](const std::vector<int> &num, const std::vector<int> &den) {
+        std::vector<int> q, r;
+        b.divide(num, den, q, r);
+        return q;
+    };
+    std::vector<std::vector<int>> ex(m), ey(m);
+    for (int i = 0; i < m; ++i) ex[i] = widen(x[i], kW, 0);
+    for (int i = 0; i < m; ++i) ey[i] = widen(y[i], kW, 0);
+    const std::vector<int> sx = total(ex), sy = total(ey);
+    std::vector<int> xbar = quotient(sx, cm), ybar = quotient(sy, cm);
+    xbar.resize(kIn);
+    ybar.resize(kIn);
+    std::vector<std::vector<int>> dx(m), dy(m), pn(m), pd(m);
+    for (int i = 0; i < m; ++i) dx[i] = sub(x[i], xbar);
+    for (int i = 0; i < m; ++i) dy[i] = sub(y[i], ybar);
+    for (int i = 0; i < m; ++i) pn[i] = b.multiply(dy[i], dx[i]);
+    const std::vector<int> num = total(pn);
+    for (int i = 0; i < m; ++i) pd[i] = b.multiply(dx[i], dx[i]);
+    const std::vector<int> den = total(pd);
+    const std::vector<int> omega = quotient(widen(num, 2 * kW, frac), den);
+    const std::vector<int> prod = b.multiply(omega, sx);
+    const std::vector<int> u = sub(widen(sy, 2 * kW, frac), prod);
+    const std::vector<int> icpt = quotient(u, cm);
+    b.outputs = omega;
+    b.outputs.insert(b.outputs.end(), icpt.begin(), icpt.end());
     return export_netlist(b, gates, n_gates, n_wires, inputs, outputs);
 }
 

@@ -360,12 +360,15 @@ struct Streams {
 // so that every slot index is a compile-time constant (no register moves);
 // after step X's MFMAs the slots of alpha(X - MR + 1) and beta(X - MR + 1),
 // no longer needed, receive alpha(X + D + 1) and beta(X + D + 1).
-template <int MR, int NC, class Init>
+// DP overrides the prefetch depth; steps X0 .. X0 + nsteps - 1 of the
+// stream are run (default: all of them).  A start X0 > 0 needs MR = 1, whose
+// steps use no digit tile of an earlier step.
+template <int MR, int NC, int DP = 0, class Init>
 __device__ __forceinline__ void toeplitz_gemm(const Operands &o, int lane, v16i (&acc)[MR][NC][4],
-                                              Init init) {
-    constexpr int D = MR > 2 ? MR : 2, R = MR + D;
+                                              Init init, int X0 = 0, int nsteps = -1) {
+    constexpr int D = DP > 0 ? DP : (MR > 2 ? MR : 2), R = MR + D;
     const Streams S(o, MR, lane, 0);
-    const int steps = o.ell * S.P;
+    const int steps = nsteps >= 0 ? nsteps : o.ell * S.P;
     uint32_t vk[4], vd[NC];
 #pragma unroll
     for (int t = 0; t < 4; ++t) vk[t] = S.key_lane(t);
@@ -376,7 +379,7 @@ __device__ __forceinline__ void toeplitz_gemm(const Operands &o, int lane, v16i 
     for (int i = 1; i < MR; ++i)
 #pragma unroll
         for (int c = 0; c < NC; ++c) sb[R - i][c] = v4i{};  // beta(-i) = 0
-    Cursor q = S.at(0);
+    Cursor q = S.at(X0);
 #pragma unroll
     for (int x = 0; x <= D; ++x) {
 #pragma unroll
@@ -588,6 +591,131 @@ __global__ __launch_bounds__(256, OCC) void mfma_gemm2_kernel(MfmaArgs a, int pa
     load_tiles<MR, NC>(base, (size_t)K1 * N, tk, lane, old);
     toeplitz_gemm<MR, NC>(o, lane, acc, [&]() { seed_acc<MR, NC>(old, acc); });
     store_tiles<MR, NC>(base, (size_t)K1 * N, tk, lane, acc);
+}
+
+// ------------------------------------------------------- K-split GEMMs ----
+//
+// At small batches the GEMMs above occupy a few dozen CUs and their time is
+// the length of one wave's MFMA chain (MR x 4 limbs x ell x (NB + MR - 1))
+// plus the load latencies along it.  These variants split the contraction:
+// a workgroup has ell x H waves for one (unit, row block, gate tile), wave
+// (l, c) runs the skewed schedule over key polynomial l alone (its digit
+// block and key tiles start at l) and, with H = 2, over half of its K-blocks
+// (MR = 1 only), with a deeper prefetch.  The partial results, limbs already
+// combined, are summed through LDS by wave 0, which also does the
+// read-modify-write of the output.
+constexpr int kSplitD = 4;  // prefetch depth of the K-split GEMMs
+
+__device__ __forceinline__ Task decode_split(int GT, int RB) {
+    int task = blockIdx.x;
+    Task t;
+    t.gt0 = task % GT;  // gate tile fastest: each XCD keeps its tiles' digits
+    task /= GT;
+    t.rb = task % RB;
+    t.unit = task / RB;
+    t.nc_valid = 1;
+    return t;
+}
+
+template <int MR>
+__device__ __forceinline__ void split_reduce_store(uint32_t *red, int w, int waves, int lane,
+                                                   const v16i (&acc)[MR][1][4], uint32_t *base,
+                                                   size_t gate_stride, const Task &tk) {
+    uint32_t v[MR][16];
+#pragma unroll
+    for (int r = 0; r < MR; ++r)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) v[r][e] = combine<MR, 1>(acc, r, 0, e);
+    if (w > 0) {
+#pragma unroll
+        for (int r = 0; r < MR; ++r)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) red[(((w - 1) * MR + r) * 16 + e) * 64 + lane] = v[r][e];
+    }
+    __syncthreads();
+    if (w != 0) return;
+    for (int i = 1; i < waves; ++i)
+#pragma unroll
+        for (int r = 0; r < MR; ++r)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) v[r][e] += red[(((i - 1) * MR + r) * 16 + e) * 64 + lane];
+#pragma unroll
+    for (int r = 0; r < MR; ++r) {
+        uint32_t *row = tile_row<MR>(base, gate_stride, tk, 0, r, lane);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            *reinterpret_cast<uint4 *>(row + 8 * q) =
+                make_uint4(v[r][4 * q], v[r][4 * q + 1], v[r][4 * q + 2], v[r][4 * q + 3]);
+    }
+}
+
+// Runs wave (l, c)'s part of the contraction; with `seed` (wave 0 of a
+// read-modify-write unit) the old output values start the accumulators.
+template <int MR, int H>
+__device__ __forceinline__ void split_part(const Operands &o, int c, int lane, bool seed, uint32_t *base,
+                                           size_t gate_stride, const Task &tk, v16i (&acc)[MR][1][4]) {
+    static_assert(H == 1 || MR == 1, "K-block chunks need the one-row schedule");
+    const int NB = o.NB;
+    const int X0 = c * (NB / H), nsteps = H == 1 ? NB + MR - 1 : NB / H;
+#pragma unroll
+    for (int r = 0; r < MR; ++r)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[r][0][t] = v16i{};
+    if (seed) {
+        uint4 old[MR][1][4];
+        load_tiles<MR, 1>(base, gate_stride, tk, lane, old);
+        toeplitz_gemm<MR, 1, kSplitD>(o, lane, acc, [&]() { seed_acc<MR, 1>(old, acc); }, X0, nsteps);
+    } else {
+        toeplitz_gemm<MR, 1, kSplitD>(o, lane, acc, []() {}, X0, nsteps);
+    }
+}
+
+// Stage 1, K-split: units as in mfma_gemm1_kernel.
+template <int MR, int H>
+__global__ __launch_bounds__(64 * kMaxEll * H) void mfma_gemm1_split_kernel(MfmaArgs a, int party, int bit,
+                                                                             int live) {
+    __shared__ uint32_t red[(kMaxEll * H - 1) * MR * 16 * 64];
+    const int N = a.N, NB = N / 32, ND = 2 * NB - 1, K1 = a.k + 1, ell = a.ell;
+    const int GT = a.GP / 32;
+    const Task tk = decode_split(GT, NB / MR);
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64)), l = w / H, c = w % H;
+    const int kind = tk.unit / live, j = tk.unit % live;
+    const size_t poly_tiles = (size_t)4 * ND * kTileBytes;
+    Operands o;
+    o.A = (kind == 0 ? a.bk + (((size_t)party * a.n + bit) * 3 + 0) * ell * poly_tiles
+                     : a.evk + (size_t)j * ell * poly_tiles) +
+          (size_t)l * poly_tiles;
+    o.B = a.U + (((size_t)j * ell + l) * GT + tk.gt0) * NB * kTileBytes;
+    o.b_poly = (uint32_t)((size_t)GT * NB * kTileBytes);
+    o.ell = 1; o.NB = NB; o.mb0 = tk.rb * MR; o.nc_valid = 1;
+    uint32_t *base = kind == 0 ? a.acc + (size_t)j * N : a.W + (size_t)j * a.GP * N;
+    const size_t gate_stride = kind == 0 ? (size_t)K1 * N : (size_t)N;
+    v16i acc[MR][1][4];
+    split_part<MR, H>(o, c, lane, kind == 0 && w == 0, base, gate_stride, tk, acc);
+    split_reduce_store<MR>(red, w, ell * H, lane, acc, base, gate_stride, tk);
+}
+
+// Stage 2, K-split: units as in mfma_gemm2_kernel.
+template <int MR, int H>
+__global__ __launch_bounds__(64 * kMaxEll * H) void mfma_gemm2_split_kernel(MfmaArgs a, int party, int bit) {
+    __shared__ uint32_t red[(kMaxEll * H - 1) * MR * 16 * 64];
+    const int N = a.N, NB = N / 32, ND = 2 * NB - 1, K1 = a.k + 1, ell = a.ell;
+    const int GT = a.GP / 32;
+    const Task tk = decode_split(GT, NB / MR);
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64)), l = w / H, c = w % H;
+    const size_t poly_tiles = (size_t)4 * ND * kTileBytes;
+    Operands o;
+    o.A = a.bk + ((((size_t)party * a.n + bit) * 3 + 1 + tk.unit) * ell + l) * poly_tiles;
+    o.B = a.V + ((size_t)l * GT + tk.gt0) * NB * kTileBytes;
+    o.b_poly = (uint32_t)((size_t)GT * NB * kTileBytes);
+    o.ell = 1; o.NB = NB; o.mb0 = tk.rb * MR; o.nc_valid = 1;
+    uint32_t *base = a.acc + (size_t)(tk.unit == 0 ? 0 : 1 + party) * N;
+    const size_t gate_stride = (size_t)K1 * N;
+    v16i acc[MR][1][4];
+    split_part<MR, H>(o, c, lane, w == 0, base, gate_stride, tk, acc);
+    split_reduce_store<MR>(red, w, ell * H, lane, acc, base, gate_stride, tk);
 }
 
 // ---------------------------------------------------- limb-split GEMMs ----
@@ -825,8 +953,8 @@ __global__ __launch_bounds__(256, OCC) void mfma_gemm2_limb_kernel(MfmaArgs a, i
 struct GemmShape {
     int MR, NC;
 };
-constexpr GemmShape kShapes[] = {{8, 1}, {4, 2}, {4, 1}, {2, 1}, {8, 2}};
-constexpr int kNumShapes = 5;
+constexpr GemmShape kShapes[] = {{8, 1}, {4, 2}, {4, 1}, {2, 1}, {8, 2}, {2, 1}, {1, 1}, {1, 1}};
+constexpr int kNumShapes = 8;
 
 template <int V>
 struct ShapeOf;
@@ -835,11 +963,19 @@ template <> struct ShapeOf<1> { static constexpr int MR = 4, NC = 2, OCC = 2; st
 template <> struct ShapeOf<2> { static constexpr int MR = 4, NC = 1, OCC = 3; static constexpr bool LIMB = true; };
 template <> struct ShapeOf<3> { static constexpr int MR = 2, NC = 1, OCC = 2; static constexpr bool LIMB = false; };
 template <> struct ShapeOf<4> { static constexpr int MR = 8, NC = 2, OCC = 1; static constexpr bool LIMB = true; };
+// OCC = 0 marks the K-split kernels (ell x H waves per workgroup).
+template <> struct ShapeOf<5> { static constexpr int MR = 2, NC = 1, OCC = 0, H = 1; static constexpr bool LIMB = false; };
+template <> struct ShapeOf<6> { static constexpr int MR = 1, NC = 1, OCC = 0, H = 1; static constexpr bool LIMB = false; };
+template <> struct ShapeOf<7> { static constexpr int MR = 1, NC = 1, OCC = 0, H = 2; static constexpr bool LIMB = false; };
 
 template <int V>
 static void launch_g1(const MfmaArgs &a, int party, int bit, int live, int GT, int NB, hipStream_t s) {
     using S = ShapeOf<V>;
-    if constexpr (S::LIMB) {
+    if constexpr (S::OCC == 0) {
+        const unsigned g = (unsigned)(2 * live * (NB / S::MR) * GT);
+        hipLaunchKernelGGL((mfma_gemm1_split_kernel<S::MR, S::H>), dim3(g), dim3(64 * a.ell * S::H), 0, s, a,
+                           party, bit, live);
+    } else if constexpr (S::LIMB) {
         const unsigned g = (unsigned)(2 * live * (NB / S::MR) * ((GT + S::NC - 1) / S::NC));
         hipLaunchKernelGGL((mfma_gemm1_limb_kernel<S::MR, S::NC, S::OCC>), dim3(g), dim3(256), 0, s, a, party,
                            bit, live);
@@ -853,7 +989,11 @@ static void launch_g1(const MfmaArgs &a, int party, int bit, int live, int GT, i
 template <int V>
 static void launch_g2(const MfmaArgs &a, int party, int bit, int GT, int NB, hipStream_t s) {
     using S = ShapeOf<V>;
-    if constexpr (S::LIMB) {
+    if constexpr (S::OCC == 0) {
+        const unsigned g = (unsigned)(2 * (NB / S::MR) * GT);
+        hipLaunchKernelGGL((mfma_gemm2_split_kernel<S::MR, S::H>), dim3(g), dim3(64 * a.ell * S::H), 0, s, a,
+                           party, bit);
+    } else if constexpr (S::LIMB) {
         const unsigned g = (unsigned)(2 * (NB / S::MR) * ((GT + S::NC - 1) / S::NC));
         hipLaunchKernelGGL((mfma_gemm2_limb_kernel<S::MR, S::NC, S::OCC>), dim3(g), dim3(256), 0, s, a, party,
                            bit);
@@ -870,6 +1010,9 @@ static void gemm1(int v, const MfmaArgs &a, int party, int bit, int live, int GT
         case 2: launch_g1<2>(a, party, bit, live, GT, NB, s); break;
         case 3: launch_g1<3>(a, party, bit, live, GT, NB, s); break;
         case 4: launch_g1<4>(a, party, bit, live, GT, NB, s); break;
+        case 5: launch_g1<5>(a, party, bit, live, GT, NB, s); break;
+        case 6: launch_g1<6>(a, party, bit, live, GT, NB, s); break;
+        case 7: launch_g1<7>(a, party, bit, live, GT, NB, s); break;
         default: launch_g1<0>(a, party, bit, live, GT, NB, s);
     }
 }
@@ -879,6 +1022,9 @@ static void gemm2(int v, const MfmaArgs &a, int party, int bit, int GT, int NB, 
         case 2: launch_g2<2>(a, party, bit, GT, NB, s); break;
         case 3: launch_g2<3>(a, party, bit, GT, NB, s); break;
         case 4: launch_g2<4>(a, party, bit, GT, NB, s); break;
+        case 5: launch_g2<5>(a, party, bit, GT, NB, s); break;
+        case 6: launch_g2<6>(a, party, bit, GT, NB, s); break;
+        case 7: launch_g2<7>(a, party, bit, GT, NB, s); break;
         default: launch_g2<0>(a, party, bit, GT, NB, s);
     }
 }
@@ -976,11 +1122,20 @@ static int default_shape(int NB) {
     return kNumShapes - 1;
 }
 
+// Untuned shapes by batch size, from timings at N = 1024 on MI355X: K-split
+// shapes while a launch covers few CUs, then the skewed shape, then the
+// first limb-split shape that fits (stage 2, with a third of stage 1's
+// products, keeps the skewed shape).
+static void default_shapes(int NB, int GT, int &v1, int &v2) {
+    v1 = GT <= 2 ? 6 : GT <= 4 ? 5 : GT <= 12 ? 3 : default_shape(NB);
+    v2 = GT <= 4 ? 6 : GT <= 12 ? 5 : 3;
+}
+
 // Tile shapes for a batch of GT gate tiles: forced by mk_set_tiles, else the
 // autotuned choice for this size, else the default.
 static void shapes_for(const mk_ctx *ctx, int GT, int &v1, int &v2) {
     const DeviceKeys &D = ctx->dev;
-    v1 = v2 = default_shape(ctx->p.N / 32);
+    default_shapes(ctx->p.N / 32, GT, v1, v2);
     auto it = D.tuned_tiles.find(GT);
     if (it != D.tuned_tiles.end()) {
         v1 = it->second.first;
@@ -1113,7 +1268,7 @@ static int tune_shapes(mk_ctx *ctx, size_t count, hipStream_t s, hipEvent_t e0, 
     const int party = P.k - 1, live = std::min(P.k + 1, party + 2);
     constexpr int kReps = 4;
     float best[2] = {3.0e38f, 3.0e38f};
-    pick[0] = pick[1] = default_shape(NB);
+    default_shapes(NB, GT, pick[0], pick[1]);
     for (int which = 0; which < 2; ++which)
         for (int v = 0; v < kNumShapes; ++v) {
             if (NB % kShapes[v].MR) continue;

@@ -110,6 +110,25 @@ def test_lr_step_small(torch_cuda):
     assert np.array_equal(mi.from_bits(dec.reshape(2, 16)), lr.replica_step(X, y, w))
 
 
+def test_lr_formula_small(torch_cuda):
+    """Closed-form regression (Alg. 7) on 4 data sets of m = 8 pairs, pair i
+    encrypted by party i mod 2: sampled gates word for word against the
+    oracle, slopes and intercepts decrypted against the integer replica."""
+    import paper_2205_05825_amd as mk
+    K, ctx = helpers.gpu_world("C1B")
+    m, sets = 8, 4
+    x, y, _, _ = mi.formula_lr_data(sets, m, seed=17)
+    circ = mk.build_lr_formula(m)
+    bits = lr.formula_input_bits(x, y)
+    owner = lr.formula_input_owner(m, 2)
+    in_ct = np.stack([tfhe.encrypt(K, int(owner[i]), bits[i], seed=700 + i) for i in range(len(bits))])
+    outs = helpers.sampled_level_parity("C1B", circ, in_ct, lambda c: _eval(torch_cuda, ctx, c, in_ct, 1),
+                                        8, seed=71)
+    dec = np.stack([tfhe.decrypt(K, o) for o in outs])
+    got = list(zip(mi.from_bits(dec[:16].T).tolist(), mi.from_bits(dec[16:].T).tolist()))
+    assert got == [lr.formula_replica(a, b) for a, b in zip(x, y)]
+
+
 @pytest.mark.parametrize("path", [0, 1])
 def test_graph_replays_match_eager(torch_cuda, path):
     """An operator captured as a HIP graph: three replays on new inputs, with

@@ -199,7 +199,7 @@ def test_not_gate(torch_cuda):
     assert np.array_equal(out.cpu().numpy().view(np.uint32), tfhe.lwe_not(c))
 
 
-@pytest.mark.parametrize("shape", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("shape", [0, 1, 2, 3, 4, 5, 6, 7])
 def test_every_tile_shape_is_bit_identical(torch_cuda, shape):
     """The GEMM tile shapes only change speed: outputs of every shape equal
     the oracle's (C1 gates) and each other's (C2 partial rotation)."""
@@ -265,18 +265,18 @@ def test_split_batches_are_bit_identical(torch_cuda):
 
 
 def test_smallest_ring_shapes(torch_cuda):
-    """N = 128 (4 K-blocks): the 256-row shapes are refused, the default is
-    the first shape that fits, and every admissible shape matches the
-    oracle, ragged gate tiles included."""
+    """N = 128 (4 K-blocks): the 256-row shapes are refused, the default for
+    large batches is the first shape that fits, and every admissible shape
+    matches the oracle, ragged gate tiles included."""
     K, ctx = helpers.gpu_world("C1S")
-    assert ctx.get_tiles(100) == (1, 1)
+    assert ctx.get_tiles(100) == (5, 6) and ctx.get_tiles(1000) == (1, 3)
     for bad in (0, 4):
         with pytest.raises(Exception):
             ctx.set_tiles(bad, bad)
     types, m1, m2 = mi.gate_batch(45, seed=14)
     c1, c2 = _workload(K, types, m1, m2, seed=140)
     ref = helpers.oracle_gates("C1S", types, c1, c2)
-    for shape in (1, 2, 3):
+    for shape in (1, 2, 3, 5, 6, 7):
         ctx.set_tiles(shape, shape)
         try:
             got = _gates_on_gpu(torch_cuda, ctx, types, c1, c2, 1)
@@ -284,14 +284,14 @@ def test_smallest_ring_shapes(torch_cuda):
             ctx.set_tiles(-1, -1)
         assert np.array_equal(got, ref), shape
     v1, v2, ms = ctx.autotune(45)
-    assert v1 in (1, 2, 3) and v2 in (1, 2, 3)
-    assert ms[0] == 0 and ms[4] == 0 and ms[5] == 0 and ms[9] == 0
+    assert v1 in (1, 2, 3, 5, 6, 7) and v2 in (1, 2, 3, 5, 6, 7)
+    assert ms[0] == 0 and ms[4] == 0 and ms[8] == 0 and ms[12] == 0
 
 
 def test_autotune_picks_valid_shapes(torch_cuda):
     K, ctx = helpers.gpu_world("C1")
     v1, v2, ms = ctx.autotune(300)
-    assert v1 in range(5) and v2 in range(5)
+    assert v1 in range(8) and v2 in range(8)
     assert ctx.get_tiles(300) == (v1, v2)
     assert all(m > 0 for m in ms)     # N/32 = 8 admits every shape
     types, m1, m2 = mi.gate_batch(300, seed=13)

@@ -151,3 +151,4 @@ def test_c5_lr_step_full(torch_cuda):
     print("C5 LR step: %d levels, %d gates, widest level %d, %.1f s, %.0f gates/s"
           % (levels, live, width, timing["dt"], live / timing["dt"]))
     assert np.array_equal(mi.from_bits(dec.reshape(d, 16)), lr.replica_step(X, y, w))
+

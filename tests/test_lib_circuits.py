@@ -33,6 +33,12 @@ def test_lr_netlist_matches_oracle(m, d):
     _same(mk.build_lr_step(m, d), lr.build_netlist(m, d))
 
 
+@pytest.mark.parametrize("m,frac", [(1, 8), (3, 0), (16, 8), (64, 8)])
+def test_lr_formula_netlist_matches_oracle(m, frac):
+    import paper_2205_05825_amd as mk
+    _same(mk.build_lr_formula(m, frac), lr.build_formula_netlist(m, frac))
+
+
 @pytest.mark.parametrize("t", range(7))
 def test_naive_gate_netlists_match_oracle(t):
     import paper_2205_05825_amd as mk

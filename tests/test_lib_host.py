@@ -106,13 +106,15 @@ def test_error_codes():
 def test_tile_shape_arguments():
     import paper_2205_05825_amd as mk
     ctx = mk.Context(helpers.lib_params(OP.C1), 3)
-    assert ctx.get_tiles(1000) == (0, 0)
+    assert ctx.get_tiles(1000) == (0, 3)
+    # untuned small batches take the K-split and skewed shapes
+    assert ctx.get_tiles(20) == (6, 6) and ctx.get_tiles(100) == (5, 6) and ctx.get_tiles(300) == (3, 5)
     ctx.set_tiles(2, 1)
     assert ctx.get_tiles(1000) == (2, 1)
     ctx.set_tiles(-1, -1)
-    assert ctx.get_tiles(1000) == (0, 0)
+    assert ctx.get_tiles(1000) == (0, 3)
     with pytest.raises(mk.MkError):
-        ctx.set_tiles(5, 0)
+        ctx.set_tiles(8, 0)
     assert ctx.get_split(1000) == 1
     ctx.set_split(1000, 2)
     assert ctx.get_split(1000) == 2 and ctx.get_split(1024) == 2 and ctx.get_split(900) == 1
@@ -123,7 +125,7 @@ def test_tile_shape_arguments():
         with pytest.raises(mk.MkError):
             ctx.set_split(1000, bad)
     small = mk.Context(helpers.lib_params(OP.C1S), 3)   # N/32 = 4: 256-row shapes refused
-    assert small.get_tiles(1000) == (1, 1)
+    assert small.get_tiles(1000) == (1, 3)
     with pytest.raises(mk.MkError):
         small.set_tiles(0, 1)
     with pytest.raises(mk.MkError):

@@ -143,6 +143,82 @@ def test_lr_netlist_config5_size():
     assert np.array_equal(mi.from_bits(out.reshape(4, 16)), lr.replica_step(X, y, w))
 
 
+def test_divider_quotient_bits_beyond_its_range():
+    """The closed-form regression relies on the divider returning the low k
+    bits of the truncated quotient for every dividend: 2k-bit dividends and
+    k-bit divisors, exhaustively at k = 4, including quotients that overflow
+    k bits."""
+    k = 4
+    a = np.arange(-(1 << (2 * k - 1)), 1 << (2 * k - 1))
+    b = np.arange(-(1 << (k - 1)), 1 << (k - 1))
+    a, b = (v.ravel() for v in np.meshgrid(a, b[b != 0], indexing="ij"))
+    out = _run(C.divider(k, 2 * k), 2 * k, a, b, kb=k)
+    qe, _ = _trunc_div(a, b)
+    assert np.array_equal(mi.from_bits(out[:k].T), _wrap(qe, k))
+
+
+def _least_squares(x, y):
+    A = np.vstack([np.asarray(x, float), np.ones(len(x))]).T
+    return np.linalg.lstsq(A, np.asarray(y, float), rcond=None)[0]
+
+
+@pytest.mark.parametrize("m,sets", [(64, 150), (16, 100)])
+def test_lr_formula_replica_tracks_least_squares(m, sets):
+    """§3.4 Eqs. (2)-(3): the integer closed form against float least
+    squares.  With x̄, ȳ truncated (errors below 1), the centred sums are off
+    by less than m each, so the slope is off by at most
+    m (1 + |ω|) / sum (x - x̄)^2 + 2^-F, and the intercept by that times |x̄|
+    plus 2^-F."""
+    x, y, _, _ = mi.formula_lr_data(sets, m, seed=m)
+    f = 2.0 ** -lr.FRAC_F
+    for xs, ys in zip(x, y):
+        om, b = lr.formula_replica(xs, ys)
+        w, c = _least_squares(xs, ys)
+        sxx = ((xs - xs.mean()) ** 2).sum()
+        slope_tol = m * (1 + abs(w)) / sxx + f
+        assert abs(om * f - w) <= slope_tol
+        assert abs(b * f - c) <= slope_tol * abs(xs.mean()) + f
+
+
+def test_lr_formula_exact_on_a_centred_line():
+    """With integer means the centred sums are exact: y = 2x + 3 over
+    x = -3..3 (twice) gives slope 2 and intercept 3 exactly (Q8.8)."""
+    x = np.tile(np.arange(-3, 4), 2)
+    om, b = lr.formula_replica(x, 2 * x + 3)
+    assert (om, b) == (512, 768)
+    # constant y: slope 0, intercept y
+    assert lr.formula_replica(x, np.full(14, -5)) == (0, -5 * 256)
+
+
+def test_lr_formula_netlist_matches_replica():
+    """The netlist equals the integer definition, including full-range int8
+    data where every sum wraps, and on the regression workload."""
+    rng = np.random.default_rng(12)
+    x = rng.integers(-128, 128, size=(40, 5))
+    y = rng.integers(-128, 128, size=(40, 5))
+    xw, yw, _, _ = mi.formula_lr_data(4, 5, seed=3)
+    x, y = np.concatenate([x, xw]), np.concatenate([y, yw])
+    keep = []
+    for i in range(len(x)):
+        try:
+            keep.append((i, lr.formula_replica(x[i], y[i])))
+        except ZeroDivisionError:
+            pass
+    idx = [i for i, _ in keep]
+    assert len(idx) > 30
+    out = C.eval_plain(lr.build_formula_netlist(5), lr.formula_input_bits(x[idx], y[idx]))
+    got = list(zip(mi.from_bits(out[:16].T).tolist(), mi.from_bits(out[16:].T).tolist()))
+    assert got == [v for _, v in keep]
+
+
+def test_lr_formula_netlist_workload_size():
+    x, y, _, _ = mi.formula_lr_data(3, 64, seed=5)
+    nl = lr.build_formula_netlist(64)
+    out = C.eval_plain(nl, lr.formula_input_bits(x, y))
+    got = list(zip(mi.from_bits(out[:16].T).tolist(), mi.from_bits(out[16:].T).tolist()))
+    assert got == [lr.formula_replica(a, b) for a, b in zip(x, y)]
+
+
 @pytest.mark.parametrize("op,k", [("add", 3), ("sub", 2), ("mul", 2), ("div", 2)])
 def test_encrypted_operators_exhaustive_toy(op, k):
     """Encrypted evaluation of every operand pair at the toy shape: operand a
