@@ -184,6 +184,46 @@ def formula_lr(torch, mk, ctx, sets, m=64, frac=8):
             "seconds": dt, "gates_per_s": sets * live / dt, "ms_per_level": dt * 1e3 / levels}
 
 
+PARTY_SETS = {4: dict(C2, k=4), 8: dict(C2, k=8, bk_noise_log2=31, ks_noise_log2=16)}
+
+
+def party_scaling(torch, mk, batch, ks):
+    """Table 8's party counts on the bootstrapped gate: `batch` mixed gates at
+    the Table 7 shape with k parties (k = 8 with the retuned key noise), in1
+    from party 0 and in2 from party k-1, tile shapes autotuned; the second
+    of two runs is timed and every output is decrypted."""
+    dev = torch.device("cuda:0")
+    res = {}
+    for k in ks:
+        P = mk.Params(**PARTY_SETS[k])
+        ctx = mk.Context(P, SEED + k)
+        for i in range(k):
+            ctx.keygen(i, (SEED + 100 * k + i) & 0xFFFFFFFFFFFFFFFF)
+        ctx.upload()
+        types, m1, m2 = mi.gate_batch(batch, seed=SEED)
+        c1, c2 = ctx.encrypt(0, m1, seed=200), ctx.encrypt(k - 1, m2, seed=201)
+        t = torch.from_numpy(types).to(dev)
+        a = torch.from_numpy(c1.view(np.int32)).to(dev)
+        b = torch.from_numpy(c2.view(np.int32)).to(dev)
+        out = torch.zeros_like(a)
+        tiles = ctx.autotune(batch)
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.bootstrap_gate(t, a, b, out)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        want = np.array([mi.plain_gate(int(x), int(y), int(z)) for x, y, z in zip(types, m1, m2)])
+        assert np.array_equal(ctx.decrypt(out.cpu().numpy().view(np.uint32)), want), "k=%d" % k
+        res[str(k)] = {"gates_per_s": batch / dt, "ms_per_batch": dt * 1e3, "tiles": list(tiles[:2]),
+                       "cmux_steps": k * P.n}
+        ctx.close()
+        del a, b, out
+        torch.cuda.empty_cache()
+        print("bench: %d parties measured" % k, file=sys.stderr, flush=True)
+    return res
+
+
 def naive_comparison(torch, mk, ctx, batch):
     """Table 2 on one MI355X: every gate type run as the scheme's single
     bootstrapped gate (NOT: the free linear NOT) and as its NAND-only
@@ -241,6 +281,8 @@ def main():
     ap.add_argument("--cpu-gates-per-core", type=int, default=1)
     ap.add_argument("--operator-pairs", type=int, default=1024,
                     help="operand pairs of the 16-bit adder timed through a HIP graph (0: skip)")
+    ap.add_argument("--party-gates", type=int, default=1024,
+                    help="gates per batch of the 4- and 8-party runs (0: skip)")
     ap.add_argument("--formula-sets", type=int, default=0,
                     help="data sets of the closed-form regression run (m = 64 pairs each; 0: skip)")
     ap.add_argument("--naive-pairs", type=int, default=1024,
@@ -382,6 +424,10 @@ def main():
     if head == mk.PATH_MFMA_I8 and args.operator_pairs > 0:
         res["operators"] = operator_rate(torch, mk, ctx, args.operator_pairs)
         print("bench: operators measured", file=sys.stderr, flush=True)
+    if head == mk.PATH_MFMA_I8 and args.party_gates > 0:
+        res["party_scaling"] = party_scaling(torch, mk, args.party_gates, (4, 8))
+        res["party_scaling"]["2"] = {"gates_per_s": value, "ms_per_batch": sec * 1e3,
+                                     "tiles": list(tiles[:2]), "cmux_steps": C2["k"] * C2["n"]}
     if head == mk.PATH_MFMA_I8 and args.formula_sets > 0:
         res["lr_formula"] = formula_lr(torch, mk, ctx, args.formula_sets)
         print("bench: closed-form regression measured", file=sys.stderr, flush=True)

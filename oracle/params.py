@@ -57,6 +57,14 @@ C2 = Params(k=2, n=560, N=1024, bk_ell=3, ks_t=8,
 # Table 7 shape with 4 parties.
 C3 = Params(k=4, n=560, N=1024, bk_ell=3, ks_t=8,
             bk_noise_log2=30, ks_noise_log2=15, lwe_noise_log2=15)
+# Table 7 shape with 8 parties, retuned.  With the Table 7 noise the
+# rotation's phase error grows with k n N (k N + 2) to about 2^-5.4 at k = 8,
+# which leaves the gate windows a margin of only 3.6 standard deviations
+# (a failure rate near 4e-4 per gate).  Key noise 2^-31 on the bootstrapping
+# key and 2^-16 on the key-switching key restore about 6.8 deviations, the
+# margin of the 4-party set.
+C8 = Params(k=8, n=560, N=1024, bk_ell=3, ks_t=8,
+            bk_noise_log2=31, ks_noise_log2=16, lwe_noise_log2=15)
 # Small shapes for fast encrypted tests (decryptable).
 TOY = Params(k=2, n=16, N=64, bk_ell=3, ks_t=8,
              bk_noise_log2=30, ks_noise_log2=24, lwe_noise_log2=20)

@@ -69,6 +69,29 @@ def test_c3_gate_parity_four_parties(torch_cuda):
     assert np.array_equal(got[idx], helpers.oracle_gates("C3", types, c1, c2, idx))
 
 
+def test_c8_gate_parity_eight_parties(torch_cuda):
+    """Single gates with 8 parties (Table 8's largest party count) at the
+    Table 7 shape with the retuned key noise: in1 from party 0, in2 from
+    party 7; every output decrypted, three word for word against the
+    oracle."""
+    K, ctx = helpers.gpu_world("C8")
+    types, m1, m2 = mi.gate_batch(48, seed=38)
+    c1 = tfhe.encrypt(K, 0, m1, seed=380)
+    c2 = tfhe.encrypt(K, 7, m2, seed=381)
+    d = torch_cuda.device("cuda:0")
+    t = torch_cuda.from_numpy(types).to(d)
+    a = torch_cuda.from_numpy(c1.view(np.int32)).to(d)
+    b = torch_cuda.from_numpy(c2.view(np.int32)).to(d)
+    out = torch_cuda.zeros_like(a)
+    ctx.bootstrap_gate(t, a, b, out, path=1)
+    torch_cuda.cuda.synchronize()
+    got = out.cpu().numpy().view(np.uint32)
+    want = [mi.plain_gate(int(x), int(y), int(z)) for x, y, z in zip(types, m1, m2)]
+    assert tfhe.decrypt(K, got).tolist() == want
+    idx = [0, 23, 47]
+    assert np.array_equal(got[idx], helpers.oracle_gates("C8", types, c1, c2, idx))
+
+
 def test_c3_multiplier_256_pairs(torch_cuda):
     """8-bit signed multiplier, 256 pairs in [-128, 127], 4 parties; a from
     party 0, b from party 1; one batch per bootstrapping level."""

@@ -290,3 +290,29 @@ def test_measured_rotation_noise_matches_analytic(c1b_keys):
     sig2 = 2.0 ** (-2 * P.bk_noise_log2)
     analytic = P.k * P.n * P.bk_ell * P.N * (B * B / 12) * sig2 * (P.k * P.N + 2)
     assert analytic / 3 < var < analytic * 3, (var, analytic)
+
+
+def _gate_margin(P, xor):
+    """Gate window margin in standard deviations of the next rotation's input
+    phase: the rotation variance above (checked against measurement), plus key
+    switching (k N t rows of noise and the rounding to lb t bits), times the
+    pre-combination's weight (2 for AND-type, 8 for XOR-type gates), plus
+    the modulus switch; the window's half-width is 1/8 (AND-type) or 1/4."""
+    B = 1 << P.bk_log_base
+    v_br = P.k * P.n * P.bk_ell * P.N * (B * B / 12) * 2.0 ** (-2 * P.bk_noise_log2) * (P.k * P.N + 2)
+    lb = P.ks_log_base
+    v_ks = P.k * P.N * P.ks_t * 2.0 ** (-2 * P.ks_noise_log2) + P.k * P.N / 2 * 2.0 ** (-2 * lb * P.ks_t) / 12
+    v_ms = (1 + P.k * P.n / 2) * (1 / (2 * P.N)) ** 2 / 12
+    v_in = (8 if xor else 2) * (v_br + v_ks) + v_ms
+    return (0.25 if xor else 0.125) / np.sqrt(v_in)
+
+
+def test_eight_party_parameters_keep_the_margin():
+    """At k = 8 the Table 7 noise leaves gates a margin under 4 deviations;
+    the retuned set keeps at least the 4-party set's margin."""
+    stock = OP.Params(**{**OP.C8.__dict__, "bk_noise_log2": OP.C3.bk_noise_log2,
+                         "ks_noise_log2": OP.C3.ks_noise_log2})
+    for xor in (False, True):
+        assert _gate_margin(stock, xor) < 4
+        assert _gate_margin(OP.C8, xor) >= _gate_margin(OP.C3, xor) - 0.1 >= 6.5
+        assert _gate_margin(OP.C2, xor) > 11
