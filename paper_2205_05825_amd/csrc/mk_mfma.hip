@@ -672,7 +672,7 @@ __device__ __forceinline__ void split_part(const Operands &o, int c, int lane, b
 
 // Stage 1, K-split: units as in mfma_gemm1_kernel.
 template <int MR, int H>
-__global__ __launch_bounds__(64 * kMaxEll * H) void mfma_gemm1_split_kernel(MfmaArgs a, int party, int bit,
+__global__ __launch_bounds__(64 * kMaxEll * H, 2) void mfma_gemm1_split_kernel(MfmaArgs a, int party, int bit,
                                                                              int live) {
     __shared__ uint32_t red[(kMaxEll * H - 1) * MR * 16 * 64];
     const int N = a.N, NB = N / 32, ND = 2 * NB - 1, K1 = a.k + 1, ell = a.ell;
@@ -698,7 +698,7 @@ __global__ __launch_bounds__(64 * kMaxEll * H) void mfma_gemm1_split_kernel(Mfma
 
 // Stage 2, K-split: units as in mfma_gemm2_kernel.
 template <int MR, int H>
-__global__ __launch_bounds__(64 * kMaxEll * H) void mfma_gemm2_split_kernel(MfmaArgs a, int party, int bit) {
+__global__ __launch_bounds__(64 * kMaxEll * H, 2) void mfma_gemm2_split_kernel(MfmaArgs a, int party, int bit) {
     __shared__ uint32_t red[(kMaxEll * H - 1) * MR * 16 * 64];
     const int N = a.N, NB = N / 32, ND = 2 * NB - 1, K1 = a.k + 1, ell = a.ell;
     const int GT = a.GP / 32;
