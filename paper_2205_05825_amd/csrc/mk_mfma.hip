@@ -331,10 +331,12 @@ struct Streams {
     __device__ __forceinline__ void next(Cursor &q) const {
         q.a -= kTileBytes;
         q.b += kTileBytes;
-        const bool wrap = --q.rem == 0;
-        q.a += wrap ? a_wrap : 0u;
-        q.b += wrap ? b_wrap : 0u;
-        q.rem += wrap ? P : 0;
+        q.rem -= 1;
+        // all ones when rem reached 0 (integer mask: no lane-mask selects)
+        const uint32_t m = (uint32_t)((q.rem - 1) >> 31);
+        q.a += a_wrap & m;
+        q.b += b_wrap & m;
+        q.rem += P & (int)m;
     }
     // per-wave vector offsets: limb t of alpha, gate tile c of beta (gate
     // tiles beyond the batch read zeros)
@@ -734,14 +736,18 @@ __global__ __launch_bounds__(64 * kMaxEll * H, 2) void mfma_gemm2_split_kernel(M
 // tile r multiplies s(kb - r), loaded r steps earlier, by the digit tiles
 // of K-block kb.  The first MR - 1 steps of every l only fill the window,
 // so the load pipeline runs on through the l boundaries.  Rings: key tiles
-// in RA = 2 MR slots (window MR, prefetch MR), digit tiles in RB = 4 slots
-// (prefetch 3), s(X) and beta(X) in slot X mod RA / RB, the loop unrolled
-// max(RA, RB) times so that every slot index is a compile-time constant.
+// in RA = 2 MR slots (window MR, prefetch D <= MR - 1), digit tiles in
+// RB = D + 1 slots (prefetch D), s(X) and beta(X) in slot X mod RA / RB,
+// the loop unrolled RA times so that every slot index is a compile-time
+// constant; with equal prefetch distances one cursor drives both streams.
 template <int MR, int NC, class Init>
 __device__ __forceinline__ void limb_gemm(const Operands &o, int t, int lane, v16i (&acc)[MR][NC],
                                           Init init) {
-    constexpr int RA = 2 * MR, DA = MR, RB = 4, U = RA > RB ? RA : RB;
-    static_assert(U % RA == 0 && U % RB == 0, "ring sizes must divide the unroll");
+    // keys and digits are prefetched the same D steps ahead, so one cursor
+    // serves both streams (D = MR - 1, or 3 with two gate tiles to spare
+    // registers)
+    constexpr int D = NC == 1 ? MR - 1 : 3, RA = 2 * MR, RB = D + 1, U = RA;
+    static_assert(U % RB == 0, "ring sizes must divide the unroll");
     const Streams S(o, MR, lane, MR - 1);
     const int P = S.P, steps = o.ell * P, W = MR - 1;
     const uint32_t vk = S.key_lane(t);
@@ -749,31 +755,25 @@ __device__ __forceinline__ void limb_gemm(const Operands &o, int t, int lane, v1
 #pragma unroll
     for (int c = 0; c < NC; ++c) vd[c] = S.dig_lane(c);
     v4i win[RA], sb[RB][NC];
-    Cursor qa = S.at(0), qb = S.at(0);
-    // alpha(0..DA-1) and beta(0..RB-2), interleaved as the loop issues them
+    Cursor q = S.at(0);
+    // alpha(0..D-1) and beta(0..D-1), in the order the loop issues them
 #pragma unroll
-    for (int x = 0; x < (DA > RB - 1 ? DA : RB - 1); ++x) {
-        if (x < DA) {
-            win[x] = S.key(qa, vk);
-            S.next(qa);
-        }
-        if (x < RB - 1) {
+    for (int x = 0; x < D; ++x) {
+        win[x] = S.key(q, vk);
 #pragma unroll
-            for (int c = 0; c < NC; ++c) sb[x][c] = S.digits<false>(qb, vd[c]);
-            S.next(qb);
-        }
+        for (int c = 0; c < NC; ++c) sb[x][c] = S.digits<false>(q, vd[c]);
+        S.next(q);
         __builtin_amdgcn_sched_barrier(0);
     }
     init();  // may load and set acc, once the prologue's loads are in flight
     int ys = 0;  // y of the current step
-    // Step X first refills the slots step X-1 freed, alpha(X + DA) over
-    // alpha(X - MR) and beta(X + RB - 1) over beta(X - 1), then multiplies.
+    // Step X first loads alpha(X + D) over alpha(X - MR - 1) and beta(X + D)
+    // over beta(X - 1), then multiplies.
     auto step = [&](int u) {  // u = X mod U
-        win[(u + DA) % RA] = S.key(qa, vk);
-        S.next(qa);
+        win[(u + D) % RA] = S.key(q, vk);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) sb[(u + RB - 1) % RB][c] = S.digits<false>(qb, vd[c]);
-        S.next(qb);
+        for (int c = 0; c < NC; ++c) sb[(u + D) % RB][c] = S.digits<false>(q, vd[c]);
+        S.next(q);
         if (ys >= W) {
 #pragma unroll
             for (int r = 0; r < MR; ++r)
