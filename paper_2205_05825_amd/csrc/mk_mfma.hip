@@ -183,7 +183,8 @@ __device__ __forceinline__ void put_digits(int8_t *dst_l0, size_t l_stride, int 
 // read once, with 16-byte loads, into LDS; then every piece takes its 16
 // plain and 16 rotated coefficients from there: P_j = X^-a ACC_j - ACC_j,
 // (X^-a c)[m] = c[m + a] for m + a < N and -c[m + a - N] beyond.
-__global__ __launch_bounds__(256) void mfma_rotdec_kernel(MfmaArgs a, int step) {
+constexpr int kRotdecThreads = 512;
+__global__ __launch_bounds__(kRotdecThreads) void mfma_rotdec_kernel(MfmaArgs a, int step) {
     extern __shared__ __align__(16) uint32_t rows[];   // [8][N]
     const int N = a.N, K1 = a.k + 1, NB = N / 32, GT = a.GP / 32;
     const int groups = a.GP / 8;
@@ -191,7 +192,7 @@ __global__ __launch_bounds__(256) void mfma_rotdec_kernel(MfmaArgs a, int step) 
     const int tid = threadIdx.x;
     {
         const int per_row = N / 4;  // uint4 per row
-        for (int v = tid; v < 8 * per_row; v += 256) {
+        for (int v = tid; v < 8 * per_row; v += kRotdecThreads) {
             const int gi = v / per_row, c4 = v % per_row;
             const size_t gate = (size_t)g8 * 8 + gi;
             reinterpret_cast<uint4 *>(rows)[v] =
@@ -207,7 +208,7 @@ __global__ __launch_bounds__(256) void mfma_rotdec_kernel(MfmaArgs a, int step) 
     const int gt = gate / 32, L0 = gate % 32;
     const size_t l_stride = (size_t)GT * NB * kTileBytes;
     int8_t *base = a.U + ((size_t)j * a.ell * GT + gt) * NB * kTileBytes;
-    for (int item = tid / 8; item < NB * 2; item += 32) {  // item = (kb, h)
+    for (int item = tid / 8; item < NB * 2; item += kRotdecThreads / 8) {  // item = (kb, h)
         const int kb = item / 2, h = item % 2;
         const int m0 = 32 * kb + 16 * h;
         uint32_t y[16];
@@ -1166,8 +1167,8 @@ static int enqueue_steps(mk_ctx *ctx, const MfmaArgs *a, int parts, hipStream_t 
             hipStream_t s = ss[i];
             {
                 StageTimer t6(ctx, 6, s);
-                hipLaunchKernelGGL(mfma_rotdec_kernel, dim3((unsigned)(live * GT[i] * 4)), dim3(256), rows_lds,
-                                   s, a[i], st);
+                hipLaunchKernelGGL(mfma_rotdec_kernel, dim3((unsigned)(live * GT[i] * 4)), dim3(kRotdecThreads),
+                                   rows_lds, s, a[i], st);
             }
             {
                 StageTimer t4(ctx, 4, s);
