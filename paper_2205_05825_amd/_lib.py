@@ -22,6 +22,12 @@ if not os.path.exists(LIB_PATH):
         "libmktfhe.so is not built; run `python -m paper_2205_05825_amd.build` "
         "(hipcc, gfx950) first")
 
+# torch first: its streams and device pointers are handed to the library,
+# so both must run on one HIP runtime.  torch loads its own copy of the
+# runtime library, which then also satisfies this library's dependency (same
+# soname); loading this library first would bind a second runtime.
+import torch  # noqa: E402,F401
+
 _L = ctypes.CDLL(LIB_PATH)
 
 MK_OK, MK_EINVAL, MK_ENOMEM, MK_EDEVICE, MK_ESTATE, MK_EPARAM = 0, -1, -2, -3, -4, -5
