@@ -112,41 +112,75 @@ def cpu_baseline(gates_per_core: int):
 
 
 # ---------------------------------------------------------------- GPU ----
-def operator_rate(torch, mk, ctx, pairs):
-    """16-bit two's-complement adder (5k gates per pair, Alg. 3) on `pairs`
-    operand pairs, captured as one HIP graph; the timed launch follows one
-    warm-up launch, and every sum is decrypted and checked."""
+OPERATORS = {"add": "OP_ADD", "sub": "OP_SUB", "mul": "OP_MUL", "div": "OP_DIV"}
+
+
+def _operator_want(op, a, b, bits=16):
+    """Expected integer outputs (LSB-first bit rows are compared after
+    decoding): sum, difference (mod 2^bits), exact product, or truncated
+    quotient and remainder."""
+    wrap = lambda v: ((v + (1 << (bits - 1))) & ((1 << bits) - 1)) - (1 << (bits - 1))
+    if op == "add":
+        return [wrap(a + b)]
+    if op == "sub":
+        return [wrap(a - b)]
+    if op == "mul":
+        return [a * b]
+    q = np.abs(a) // np.abs(b) * np.sign(a) * np.sign(b)
+    return [wrap(q), wrap(a - q * b)]
+
+
+def operator_rate(torch, mk, ctx, pairs, op="add", graph=True):
+    """16-bit two's-complement operator (adder 5k gates, Alg. 3; subtractor
+    6k, Alg. 5; array multiplier; divider) on `pairs` operand pairs drawn
+    from int16 (divisors non-zero), a from party 0 and b from party 1.  With
+    `graph` the whole evaluation is captured as HIP graph pieces and the
+    timed launch follows one warm-up launch; otherwise one eager call is
+    timed.  Every output is decrypted and checked."""
     bits = 16
-    circ = mk.build_operator(mk.OP_ADD, bits)
+    circ = mk.build_operator(getattr(mk, OPERATORS[op]), bits)
     levels, live, width, _ = mk.circuit_stats(circ)
-    a, b = mi.operand_pairs(pairs, bits, seed=4)
+    a, b = mi.operand_pairs(pairs, bits, seed=4, nonzero_second=op == "div")
     words = C2["k"] * C2["n"] + 1
     cols = np.concatenate([mi.to_bits(a, bits).T, mi.to_bits(b, bits).T])
     in_ct = np.stack([ctx.encrypt(0 if i < bits else 1, col, seed=400 + i) for i, col in enumerate(cols)])
     dev = torch.device("cuda:0")
     inp = torch.from_numpy(np.ascontiguousarray(in_ct).view(np.int32)).to(dev)
-    out = torch.zeros((bits, pairs, words), dtype=torch.int32, device=dev)
-    for cnt in sorted({pairs, 2 * pairs, width * pairs}):   # the levels' batch sizes
-        ctx.autotune(cnt)
-    print("bench: operator autotune done; capturing the add16 graph", file=sys.stderr, flush=True)
-    g = ctx.circuit_graph(circ, inp, out)
-    try:
-        print("bench: graph of %d pieces captured; launching" % g.info()[2], file=sys.stderr, flush=True)
-        g.launch()
+    out = torch.zeros((len(circ.outputs), pairs, words), dtype=torch.int32, device=dev)
+    w = 1
+    while w <= width:            # level batch sizes the autotuner sees first
+        ctx.autotune(min(w * pairs, 65536))
+        w *= 2
+    print("bench: %s16 autotuned; %s" % (op, "capturing the graph" if graph else "running"),
+          file=sys.stderr, flush=True)
+    pieces = 0
+    if graph:
+        g = ctx.circuit_graph(circ, inp, out)
+        try:
+            pieces = g.info()[2]
+            print("bench: graph of %d pieces captured; launching" % pieces, file=sys.stderr, flush=True)
+            g.launch()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g.launch()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        finally:
+            g.close()
+    else:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        g.launch()
+        ctx.eval_circuit(circ, inp, out)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-    finally:
-        g.close()
     dec = np.stack([ctx.decrypt(x) for x in out.cpu().numpy().view(np.uint32)])
-    v = mi.from_bits(dec.T)
-    want = ((a + b + (1 << (bits - 1))) & ((1 << bits) - 1)) - (1 << (bits - 1))
-    assert np.array_equal(v, want), "adder outputs do not decrypt to the sums"
-    return {"operator": "add16", "pairs": pairs, "levels": levels, "gates_per_pair": live,
+    want = _operator_want(op, a, b, bits)
+    per = len(circ.outputs) // len(want)
+    for k, wv in enumerate(want):
+        assert np.array_equal(mi.from_bits(dec[k * per:(k + 1) * per].T), wv), "%s16 outputs" % op
+    return {"operator": op + "16", "pairs": pairs, "levels": levels, "gates_per_pair": live,
             "seconds": dt, "operators_per_s": pairs / dt, "gates_per_s": pairs * live / dt,
-            "graph": True}
+            "graph": graph, "graph_pieces": pieces}
 
 
 def formula_lr(torch, mk, ctx, sets, m=64, frac=8):
@@ -281,6 +315,9 @@ def main():
     ap.add_argument("--cpu-gates-per-core", type=int, default=1)
     ap.add_argument("--operator-pairs", type=int, default=1024,
                     help="operand pairs of the 16-bit adder timed through a HIP graph (0: skip)")
+    ap.add_argument("--all-operator-pairs", type=int, default=0,
+                    help="operand pairs of the 16-bit adder, subtractor, multiplier and divider runs "
+                         "(0: skip; minutes at 1024 pairs)")
     ap.add_argument("--party-gates", type=int, default=1024,
                     help="gates per batch of the 4- and 8-party runs (0: skip)")
     ap.add_argument("--formula-sets", type=int, default=0,
@@ -424,6 +461,10 @@ def main():
     if head == mk.PATH_MFMA_I8 and args.operator_pairs > 0:
         res["operators"] = operator_rate(torch, mk, ctx, args.operator_pairs)
         print("bench: operators measured", file=sys.stderr, flush=True)
+    if head == mk.PATH_MFMA_I8 and args.all_operator_pairs > 0:
+        res["operators_16bit"] = {op: operator_rate(torch, mk, ctx, args.all_operator_pairs, op, graph=op != "div")
+                                  for op in OPERATORS}
+        print("bench: 16-bit operators measured", file=sys.stderr, flush=True)
     if head == mk.PATH_MFMA_I8 and args.party_gates > 0:
         res["party_scaling"] = party_scaling(torch, mk, args.party_gates, (4, 8))
         res["party_scaling"]["2"] = {"gates_per_s": value, "ms_per_batch": sec * 1e3,

@@ -58,14 +58,16 @@ struct OutDesc {
     int32_t pad;
 };
 
+// Items item0 .. item0 + total / words - 1 of a level (item = gate of the
+// level x batch + instance) into abar (chunk-local).
 __global__ void precombine_circuit_kernel(const CircDesc *__restrict__ desc,
                                           const uint32_t *__restrict__ wires, size_t batch,
-                                          size_t stride, int words, int log2_2N, size_t total,
+                                          size_t stride, int words, int log2_2N, size_t item0, size_t total,
                                           uint32_t *__restrict__ abar) {
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= total) return;
-    const size_t item = idx / words;
-    const int w = (int)(idx - item * words);
+    const size_t item = item0 + idx / words;
+    const int w = (int)(idx % words);
     const size_t g = item / batch, b = item - g * batch;
     const CircDesc d = desc[g];
     uint32_t x = w == 0 ? d.cst : 0u;
@@ -298,12 +300,22 @@ static int alloc_circ_scratch(mk_ctx *ctx, size_t bytes) {
 
 // Host side of one circuit evaluation: the plan, the per-level
 // pre-combination descriptors and the device buffer layout.
+// Gates per rotation launch: wide levels (a multiplier's partial products
+// over thousands of operand pairs) run in chunks, which bounds the scratch
+// memory and keeps the MFMA path's 32-bit digit offsets, K1 ell GP N < 2^31,
+// in range.
+static size_t level_chunk(const mk_params &P) {
+    const size_t lim = (((size_t)1 << 31) - 1) / ((size_t)(P.k + 1) * P.bk_ell * P.N) / 32 * 32;
+    return std::max<size_t>(32, std::min<size_t>(lim, 65536));
+}
+
 struct CircuitRun {
     CircuitPlan P;
     std::vector<CircDesc> desc;
     std::vector<size_t> desc_off;
     std::vector<OutDesc> od;
     size_t batch = 0, stride = 0, words = 0;
+    size_t chunk = 0;  // gates per rotation launch within a level
     int path = 0, n_inputs = 0, n_outputs = 0;
     size_t wire_b = 0, desc_b = 0, od_b = 0, abar_b = 0, gate_b = 0;
     uint32_t *wires = nullptr;
@@ -359,7 +371,8 @@ int build_run(mk_ctx *ctx, const mk_circuit *c, size_t batch, size_t stride, int
     R.wire_b = ((size_t)P.total_slots * batch * stride * 4 + 255) / 256 * 256;
     R.desc_b = (R.desc.size() * sizeof(CircDesc) + 255) / 256 * 256;
     R.od_b = R.od.size() * sizeof(OutDesc);
-    const size_t maxc = (size_t)P.max_width * batch;
+    R.chunk = level_chunk(Pm);
+    const size_t maxc = std::min((size_t)P.max_width * batch, R.chunk);
     R.abar_b = (maxc * words * 4 + 255) / 256 * 256;
     R.gate_b = R.abar_b + maxc * (Pm.k + 1) * Pm.N * 4;
     return MK_OK;
@@ -409,18 +422,21 @@ int enqueue_run(mk_ctx *ctx, const CircuitRun &R, uint32_t *gate_scratch, const 
     int rc;
     for (int l = 1; l <= L; ++l) {
         const size_t count = P.levels[l].size() * batch;
-        const size_t total = count * words;
-        {
-            StageTimer tm(ctx, 0, s);
-            hipLaunchKernelGGL(precombine_circuit_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256),
-                               0, s, R.d_desc + R.desc_off[l], (const uint32_t *)R.wires, batch, stride,
-                               (int)words, log2_2N, total, abar);
+        for (size_t c0 = 0; c0 < count; c0 += R.chunk) {
+            const size_t cnt = std::min(R.chunk, count - c0);
+            const size_t total = cnt * words;
+            {
+                StageTimer tm(ctx, 0, s);
+                hipLaunchKernelGGL(precombine_circuit_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256),
+                                   0, s, R.d_desc + R.desc_off[l], (const uint32_t *)R.wires, batch, stride,
+                                   (int)words, log2_2N, c0, total, abar);
+            }
+            if (hipGetLastError() != hipSuccess) return fail(MK_EDEVICE, "circuit precombine launch failed");
+            uint32_t *dst = R.wires + ((size_t)P.level_base[l] * batch + c0) * stride;
+            if ((rc = run_blind_rotate(ctx, abar, acc, cnt, Pm.k * Pm.n, R.path, s)) ||
+                (rc = run_key_switch(ctx, acc, dst, cnt, stride, R.path, s)))
+                return rc;
         }
-        if (hipGetLastError() != hipSuccess) return fail(MK_EDEVICE, "circuit precombine launch failed");
-        if ((rc = run_blind_rotate(ctx, abar, acc, count, Pm.k * Pm.n, R.path, s)) ||
-            (rc = run_key_switch(ctx, acc, R.wires + (size_t)P.level_base[l] * batch * stride, count, stride,
-                                 R.path, s)))
-            return rc;
     }
     const size_t total = (size_t)R.n_outputs * batch * words;
     {
@@ -543,7 +559,7 @@ int mk_circuit_graph_create(mk_ctx *ctx, const mk_circuit *c, const uint32_t *in
     };
     // graph-owned device memory: wires | descriptors, the gate pipeline's
     // scratch and, on the MFMA path, the rotation's and key switch's scratch
-    const size_t maxc = (size_t)R.P.max_width * batch;
+    const size_t maxc = std::min((size_t)R.P.max_width * batch, R.chunk);
     const size_t sizes[4] = {R.wire_b + R.desc_b + R.od_b + 256, R.gate_b,
                              path == MK_PATH_MFMA_I8 ? mfma_scratch_need(ctx->p, maxc) : 0,
                              path == MK_PATH_MFMA_I8 ? ks_scratch_need(ctx->p, maxc) : 0};

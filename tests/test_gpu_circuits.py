@@ -110,6 +110,26 @@ def test_lr_step_small(torch_cuda):
     assert np.array_equal(mi.from_bits(dec.reshape(2, 16)), lr.replica_step(X, y, w))
 
 
+def test_wide_level_runs_in_chunks(torch_cuda):
+    """An 8-bit multiplier on 1100 operand pairs: its partial-product level
+    has 64 x 1100 = 70 400 gates, more than one rotation launch takes
+    (65 536), so the engine runs it in two chunks.  Sampled gates match the
+    oracle word for word; every product decrypts to a * b."""
+    import paper_2205_05825_amd as mk
+    K, ctx = helpers.gpu_world("C1B")
+    circ = mk.build_operator(mk.OP_MUL, 8)
+    _, _, width, _ = mk.circuit_stats(circ)
+    pairs = 1100
+    assert width * pairs > 65536
+    a, b = mi.operand_pairs(pairs, 8, seed=21)
+    in_ct = np.concatenate([helpers.encrypt_operands(K, a, 8, 0, 2100),
+                            helpers.encrypt_operands(K, b, 8, 1, 2200)])
+    outs = helpers.sampled_level_parity("C1B", circ, in_ct, lambda c: _eval(torch_cuda, ctx, c, in_ct, 1),
+                                        6, seed=23)
+    dec = np.stack([tfhe.decrypt(K, o) for o in outs])
+    assert np.array_equal(mi.from_bits(dec.T), a * b)
+
+
 def test_lr_formula_small(torch_cuda):
     """Closed-form regression (Alg. 7) on 4 data sets of m = 8 pairs, pair i
     encrypted by party i mod 2: sampled gates word for word against the
