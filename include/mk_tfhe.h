@@ -163,7 +163,9 @@ int mk_not(const mk_ctx *ctx, const uint32_t *in_dev, uint32_t *out_dev,
  * out[g] = Boots_{types[g]}(in1[g], in2[g]).  All pointers are device
  * memory; rows have `stride` words.  Pipeline: pre-combination and modulus
  * switch, blind rotation (path MK_PATH_I32 or MK_PATH_MFMA_I8, identical
- * bits), sample extraction, multi-key key switching.  `out` must not alias
+ * bits), sample extraction, multi-key key switching.  Batches larger than
+ * one rotation launch takes (65536 gates, fewer when (k+1)*bk_ell*N*65536
+ * reaches 2^31) run as consecutive chunks on `stream`.  `out` must not alias
  * the inputs.  Errors: MK_EINVAL (type >= MK_GATE_NOT, sizes),
  * MK_ESTATE (mk_upload_eval_key not called), MK_ENOMEM, MK_EDEVICE. */
 int mk_bootstrap_gate(mk_ctx *ctx, const uint8_t *gate_types_dev,
@@ -177,7 +179,9 @@ int mk_bootstrap_gate(mk_ctx *ctx, const uint8_t *gate_types_dev,
  * folded into the consumers' pre-combination (exact mod 2^32), gates that no
  * output depends on are skipped, and the remaining gates are levelled by
  * bootstrapping depth; every level runs as one batch of all its gates over
- * all instances.  The call returns after the work on `stream` has completed.
+ * all instances (in chunks, as in mk_bootstrap_gate, when wider than one
+ * rotation launch).  The call returns after the work on `stream` has
+ * completed.
  * Errors as mk_bootstrap_gate, plus MK_EINVAL for a malformed netlist
  * (undefined or redefined wires, gates out of topological order). */
 int mk_eval_circuit(mk_ctx *ctx, const mk_circuit *c, const uint32_t *in_dev,
@@ -223,7 +227,9 @@ int mk_circuit_stats(const mk_circuit *c, int32_t *n_levels, int64_t *live_gates
  *   mk_blind_rotate: abar_dev holds `count` rows of kn+1 uint32 values in
  *     [0, 2N) (modulus-switched b, a_1..a_k); acc_dev receives count rows of
  *     (k+1)*N words (the RLWE accumulator c_0..c_k) after the first
- *     `max_steps` CMux steps (all k*n when max_steps < 0).
+ *     `max_steps` CMux steps (all k*n when max_steps < 0).  This stage call
+ *     is not chunked: on MK_PATH_MFMA_I8, MK_EINVAL when
+ *     (k+1)*bk_ell*N*count (count rounded up to 32) reaches 2^31.
  *   mk_extract_keyswitch: acc_dev rows of (k+1)*N words -> out_dev LWE rows
  *     (sample extraction, + 1/8, key switching); MK_PATH_I32 sums the
  *     selected key-switching rows with 32-bit adds, MK_PATH_MFMA_I8 runs the

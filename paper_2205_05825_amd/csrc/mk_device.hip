@@ -494,26 +494,40 @@ int run_key_switch(mk_ctx *ctx, const uint32_t *acc, uint32_t *out, size_t count
     return fail(MK_EINVAL, "unknown path");
 }
 
+// Gates per rotation launch: larger batches (and wide circuit levels) run in
+// chunks, which bounds the scratch memory and keeps the MFMA path's 32-bit
+// digit offsets, K1 ell GP N < 2^31, in range.
+size_t rotation_chunk(const mk_params &P) {
+    const size_t lim = (((size_t)1 << 31) - 1) / ((size_t)(P.k + 1) * P.bk_ell * P.N) / 32 * 32;
+    return std::max<size_t>(32, std::min<size_t>(lim, 65536));
+}
+
 int run_gates(mk_ctx *ctx, const uint8_t *types, const uint32_t *in1, const uint32_t *in2,
               uint32_t *out, size_t count, size_t stride, int path, hipStream_t s) {
     const mk_params &P = ctx->p;
     const size_t words = lwe_words(P);
-    const size_t abar_bytes = (count * words * 4 + 255) / 256 * 256;
-    const size_t acc_bytes = count * (P.k + 1) * P.N * 4;
+    const size_t chunk = std::min(count, rotation_chunk(P));
+    const size_t abar_bytes = (chunk * words * 4 + 255) / 256 * 256;
+    const size_t acc_bytes = chunk * (P.k + 1) * P.N * 4;
     int rc = ensure_scratch(ctx, abar_bytes + acc_bytes);
     if (rc) return rc;
     uint32_t *abar = (uint32_t *)ctx->dev.scratch;
     uint32_t *acc = (uint32_t *)((char *)ctx->dev.scratch + abar_bytes);
-    const size_t total = count * words;
     const int log2_2N = __builtin_ctz(2 * P.N);
-    {
-        StageTimer tm(ctx, 0, s);
-        hipLaunchKernelGGL(precombine_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
-                           types, in1, in2, stride, (int)words, log2_2N, total, abar);
+    for (size_t c0 = 0; c0 < count; c0 += chunk) {
+        const size_t cnt = std::min(chunk, count - c0), total = cnt * words;
+        {
+            StageTimer tm(ctx, 0, s);
+            hipLaunchKernelGGL(precombine_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                               types + c0, in1 + c0 * stride, in2 + c0 * stride, stride, (int)words, log2_2N,
+                               total, abar);
+        }
+        MK_HIP(hipGetLastError(), "precombine launch");
+        if ((rc = run_blind_rotate(ctx, abar, acc, cnt, P.k * P.n, path, s)) ||
+            (rc = run_key_switch(ctx, acc, out + c0 * stride, cnt, stride, path, s)))
+            return rc;
     }
-    MK_HIP(hipGetLastError(), "precombine launch");
-    if ((rc = run_blind_rotate(ctx, abar, acc, count, P.k * P.n, path, s))) return rc;
-    return run_key_switch(ctx, acc, out, count, stride, path, s);
+    return MK_OK;
 }
 
 }  // namespace mk

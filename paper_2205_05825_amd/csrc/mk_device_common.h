@@ -30,6 +30,9 @@ struct StageTimer {
     hipEvent_t b = nullptr, e = nullptr;
 };
 int ensure_scratch(mk_ctx *ctx, size_t bytes);
+// Gates per rotation launch (mk_device.hip): larger batches and circuit
+// levels run in chunks of this size.
+size_t rotation_chunk(const mk_params &P);
 
 // Int8-MFMA path (mk_mfma.hip).
 int mfma_upload(mk_ctx *ctx, const std::vector<uint32_t> &evk, hipStream_t s);

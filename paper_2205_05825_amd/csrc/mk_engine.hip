@@ -300,15 +300,6 @@ static int alloc_circ_scratch(mk_ctx *ctx, size_t bytes) {
 
 // Host side of one circuit evaluation: the plan, the per-level
 // pre-combination descriptors and the device buffer layout.
-// Gates per rotation launch: wide levels (a multiplier's partial products
-// over thousands of operand pairs) run in chunks, which bounds the scratch
-// memory and keeps the MFMA path's 32-bit digit offsets, K1 ell GP N < 2^31,
-// in range.
-static size_t level_chunk(const mk_params &P) {
-    const size_t lim = (((size_t)1 << 31) - 1) / ((size_t)(P.k + 1) * P.bk_ell * P.N) / 32 * 32;
-    return std::max<size_t>(32, std::min<size_t>(lim, 65536));
-}
-
 struct CircuitRun {
     CircuitPlan P;
     std::vector<CircDesc> desc;
@@ -371,7 +362,7 @@ int build_run(mk_ctx *ctx, const mk_circuit *c, size_t batch, size_t stride, int
     R.wire_b = ((size_t)P.total_slots * batch * stride * 4 + 255) / 256 * 256;
     R.desc_b = (R.desc.size() * sizeof(CircDesc) + 255) / 256 * 256;
     R.od_b = R.od.size() * sizeof(OutDesc);
-    R.chunk = level_chunk(Pm);
+    R.chunk = rotation_chunk(Pm);  // wide levels run in chunks
     const size_t maxc = std::min((size_t)P.max_width * batch, R.chunk);
     R.abar_b = (maxc * words * 4 + 255) / 256 * 256;
     R.gate_b = R.abar_b + maxc * (Pm.k + 1) * Pm.N * 4;

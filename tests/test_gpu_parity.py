@@ -230,6 +230,21 @@ def test_every_tile_shape_is_bit_identical(torch_cuda, shape):
     assert np.array_equal(outs[0], outs[1])
 
 
+def test_large_batch_runs_in_chunks(torch_cuda):
+    """70 000 gates in one call, more than one rotation launch takes (65 536):
+    the call runs two chunks.  Gates on both sides of the chunk boundary
+    match the oracle word for word, and every output decrypts to its truth
+    table value."""
+    K, ctx = helpers.gpu_world("C1B")
+    types, m1, m2 = mi.gate_batch(70000, seed=31)
+    c1, c2 = _workload(K, types, m1, m2, seed=310)
+    got = _gates_on_gpu(torch_cuda, ctx, types, c1, c2, 1)
+    want = [mi.plain_gate(int(x), int(y), int(z)) for x, y, z in zip(types, m1, m2)]
+    assert tfhe.decrypt(K, got).tolist() == want
+    idx = [0, 65535, 65536, 69999]
+    assert np.array_equal(got[idx], helpers.oracle_gates("C1B", types, c1, c2, idx))
+
+
 def test_split_batches_are_bit_identical(torch_cuda):
     """A batch run as two sub-batches on two streams gives the same words as
     the whole batch and as the oracle (ragged halves: 70 gates -> 64 + 6)."""
