@@ -243,7 +243,7 @@ def test_key_switch_preserves_phase(toy_keys):
 
 # ------------------------------------------------------- whole gates ----
 
-@pytest.mark.parametrize("k", [1, 2, 3, 4])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 8])
 def test_gate_truth_tables_all_party_counts(k):
     P = OP.toy(k)
     K = tfhe.generate(P, 20 + k)
