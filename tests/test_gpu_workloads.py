@@ -94,16 +94,22 @@ def test_c8_gate_parity_eight_parties(torch_cuda):
 
 def test_c3_multiplier_256_pairs(torch_cuda):
     """8-bit signed multiplier, 256 pairs in [-128, 127], 4 parties; a from
-    party 0, b from party 1; one batch per bootstrapping level."""
+    party 0, b from party 1; one batch per bootstrapping level.  Six sampled
+    (gate, pair) items match the oracle word for word, recomputed from the
+    GPU's own inputs; every product decrypts to a * b."""
     import paper_2205_05825_amd as mk
-    ctx = helpers.lib_context("C3")
-    if not getattr(ctx, "_uploaded", False):
-        ctx.upload()
-        ctx._uploaded = True
+    K, ctx = helpers.gpu_world("C3")
     circ = mk.build_operator(mk.OP_MUL, 8)
     a, b = mi.operand_pairs(256, 8, seed=3)
     in_ct = np.concatenate([_enc_operand(ctx, a, 8, 0, 1), _enc_operand(ctx, b, 8, 1, 2)])
-    dec, dt = _run(torch_cuda, ctx, circ, in_ct)
+    timing = {}
+
+    def evaluate(c):
+        words, timing["dt"] = _words(torch_cuda, ctx, c, in_ct)
+        return words
+
+    outs = helpers.sampled_level_parity("C3", circ, in_ct, evaluate, 6, seed=33)
+    dec, dt = np.stack([ctx.decrypt(x) for x in outs]), timing["dt"]
     levels, live, width, _ = mk.circuit_stats(circ)
     print("C3 8-bit multiplier: %d pairs, %d levels, %d gates/pair, %.2f s, %.0f gates/s"
           % (256, levels, live, dt, live * 256 / dt))
