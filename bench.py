@@ -258,6 +258,34 @@ def party_scaling(torch, mk, batch, ks):
     return res
 
 
+def batch_scaling(torch, mk, ctx, sizes):
+    """The headline gate mix at larger batches (wide circuit levels run at
+    these sizes): tile shapes autotuned per size, the second of two runs
+    timed, every output decrypted."""
+    dev = torch.device("cuda:0")
+    res = {}
+    for n in sizes:
+        types, m1, m2 = mi.gate_batch(n, seed=SEED)
+        c1, c2 = ctx.encrypt(0, m1, seed=200), ctx.encrypt(1, m2, seed=201)
+        t = torch.from_numpy(types).to(dev)
+        a = torch.from_numpy(c1.view(np.int32)).to(dev)
+        b = torch.from_numpy(c2.view(np.int32)).to(dev)
+        out = torch.zeros_like(a)
+        tiles = ctx.autotune(n)
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.bootstrap_gate(t, a, b, out)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        want = np.array([mi.plain_gate(int(x), int(y), int(z)) for x, y, z in zip(types, m1, m2)])
+        assert np.array_equal(ctx.decrypt(out.cpu().numpy().view(np.uint32)), want), "batch %d" % n
+        res[str(n)] = {"gates_per_s": n / dt, "ms_per_batch": dt * 1e3, "tiles": list(tiles[:2]),
+                       "whole_gate_int8_tops": 8 * macs_per_gate(C2) * n / dt / 1e12}
+    print("bench: batch sizes measured", file=sys.stderr, flush=True)
+    return res
+
+
 def naive_comparison(torch, mk, ctx, batch):
     """Table 2 on one MI355X: every gate type run as the scheme's single
     bootstrapped gate (NOT: the free linear NOT) and as its NAND-only
@@ -318,6 +346,8 @@ def main():
     ap.add_argument("--all-operator-pairs", type=int, default=0,
                     help="operand pairs of the 16-bit adder, subtractor, multiplier and divider runs "
                          "(0: skip; minutes at 1024 pairs)")
+    ap.add_argument("--batch-sizes", default="2048,4096",
+                    help="larger batches of the same gate mix to time (comma list; empty: skip)")
     ap.add_argument("--party-gates", type=int, default=1024,
                     help="gates per batch of the 4- and 8-party runs (0: skip)")
     ap.add_argument("--formula-sets", type=int, default=0,
@@ -465,6 +495,8 @@ def main():
         res["operators_16bit"] = {op: operator_rate(torch, mk, ctx, args.all_operator_pairs, op, graph=op != "div")
                                   for op in OPERATORS}
         print("bench: 16-bit operators measured", file=sys.stderr, flush=True)
+    if head == mk.PATH_MFMA_I8 and args.batch_sizes:
+        res["batch_scaling"] = batch_scaling(torch, mk, ctx, [int(x) for x in args.batch_sizes.split(",")])
     if head == mk.PATH_MFMA_I8 and args.party_gates > 0:
         res["party_scaling"] = party_scaling(torch, mk, args.party_gates, (4, 8))
         res["party_scaling"]["2"] = {"gates_per_s": value, "ms_per_batch": sec * 1e3,
