@@ -133,3 +133,23 @@ def test_tile_shape_arguments():
     with pytest.raises(mk.MkError) as e:      # needs the uploaded key
         ctx.autotune(64, stream=0)
     assert e.value.code == -4
+
+
+def test_builder_and_parameter_limits():
+    """Argument checks on the host: netlist builder ranges, the party limit,
+    and the int8 exactness bound (k+1)*ell*N*2^14 < 2^31, which the
+    eight-party set meets and a doubled ring at eight parties does not."""
+    import paper_2205_05825_amd as mk
+    from paper_2205_05825_amd import _lib
+    n_g, n_w = ctypes.c_int32(), ctypes.c_int32()
+    for m, frac in ((0, 8), (4097, 8), (4, -1), (4, 16)):
+        assert _lib._L.mk_build_lr_formula(m, frac, None, ctypes.byref(n_g), ctypes.byref(n_w), None, None) == -1
+    for t in (-1, 7):
+        assert _lib._L.mk_build_naive_gate(t, None, ctypes.byref(n_g), ctypes.byref(n_w), None, None) == -1
+    assert _lib._L.mk_build_lr_formula(4, 8, None, None, None, None, None) == -1
+    mk.Context(helpers.lib_params(OP.C8), 1).close()
+    fields = {f: getattr(OP.C8, f) for f in helpers.FIELDS}
+    for change in ({"k": 9}, {"N": 8192}):
+        with pytest.raises(mk.MkError) as e:
+            mk.Context(mk.Params(**{**fields, **change}), 1)
+        assert e.value.code == -5, change
