@@ -153,3 +153,21 @@ def test_builder_and_parameter_limits():
         with pytest.raises(mk.MkError) as e:
             mk.Context(mk.Params(**{**fields, **change}), 1)
         assert e.value.code == -5, change
+
+
+def test_import_fails_loudly_without_the_library(tmp_path):
+    """A copy of the package without libmktfhe.so refuses to import (there is
+    no fallback implementation to run instead)."""
+    import shutil
+    import subprocess
+    import sys
+    src = os.path.join(ROOT, "paper_2205_05825_amd")
+    dst = tmp_path / "paper_2205_05825_amd"
+    dst.mkdir()
+    for f in os.listdir(src):
+        if f.endswith(".py"):
+            shutil.copy(os.path.join(src, f), dst / f)
+    r = subprocess.run([sys.executable, "-c", "import paper_2205_05825_amd"], cwd=tmp_path,
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0
+    assert "ImportError" in r.stderr and "libmktfhe.so is not built" in r.stderr
