@@ -171,3 +171,12 @@ def test_import_fails_loudly_without_the_library(tmp_path):
                        capture_output=True, text=True, timeout=300)
     assert r.returncode != 0
     assert "ImportError" in r.stderr and "libmktfhe.so is not built" in r.stderr
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The path is per GPU: bench.py --gpus 2 exits with status 2 and says so."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode == 2 and "one GPU" in r.stderr and not r.stdout
