@@ -24,7 +24,11 @@
  *             device scratch; the caller owns every ciphertext buffer.
  *   Streams   device entry points are asynchronous on the given hipStream_t
  *             (passed as void*, NULL = default stream); host entry points are
- *             synchronous.
+ *             synchronous.  Device calls on one context share its scratch
+ *             buffers, so calls on the same context must not overlap: issue
+ *             them on one stream, or order the streams.  Contexts are
+ *             independent of each other.  A context must not be used from two
+ *             threads at once.
  *   Errors    0 on success, a negative MK_E* code otherwise; no exception
  *             crosses the ABI.  mk_last_error() returns a thread-local message
  *             describing the most recent failure on the calling thread.
