@@ -9,9 +9,10 @@
 //   * every bootstrapped gate gets level 1 + max(level of its inputs);
 //   * each level's outputs get one contiguous range of wire slots, allocated
 //     first-fit over ranges freed after their last reader's level.
-// Device work per level: pre-combination gathering both operands of every
-// (gate, instance), one blind rotation over all of them, and extraction + key
-// switching straight into the level's slot range.  Wire buffer layout:
+// Device work per level, in chunks of at most one rotation launch:
+// pre-combination gathering both operands of every (gate, instance), one
+// blind rotation over all of them, and extraction + key switching straight
+// into the level's slot range.  Wire buffer layout:
 // row (slot * batch + instance) of `stride` words.
 #include <hip/hip_runtime.h>
 
@@ -254,8 +255,11 @@ int plan_circuit(const mk_circuit *c, CircuitPlan &P) {
         live.push_back({st, c->n_inputs, last});
     }
     for (int l = 1; l <= L; ++l) {
+        // A range becomes free once the level that last reads it has
+        // finished: a wide level runs in chunks, and an earlier chunk's
+        // outputs must not overwrite wires that a later chunk still reads.
         for (size_t r = 0; r < live.size();) {
-            if (live[r].last <= l) {  // read at most by this level's pre-combination
+            if (live[r].last < l) {
                 if (live[r].size) release(live[r].start, live[r].size);
                 live[r] = live.back();
                 live.pop_back();

@@ -130,6 +130,27 @@ def test_wide_level_runs_in_chunks(torch_cuda):
     assert np.array_equal(mi.from_bits(dec.T), a * b)
 
 
+def test_chunked_level_reading_reused_slots(torch_cuda):
+    """A 16-bit adder on 2200 operand pairs: its widest level (31 x 2200 =
+    68 200 gates) runs in two chunks.  The first chunk's outputs must not
+    land in wire slots that the second chunk still reads, so a level's
+    output range never reuses slots its own gates read.  Every sum decrypts
+    to a + b (mod 2^16) and sampled gates match the oracle."""
+    import paper_2205_05825_amd as mk
+    K, ctx = helpers.gpu_world("C1B")
+    circ = mk.build_operator(mk.OP_ADD, 16)
+    _, _, width, _ = mk.circuit_stats(circ)
+    pairs = 2200
+    assert width * pairs > 65536
+    a, b = mi.operand_pairs(pairs, 16, seed=22)
+    in_ct = np.concatenate([helpers.encrypt_operands(K, a, 16, 0, 2300),
+                            helpers.encrypt_operands(K, b, 16, 1, 2400)])
+    outs = helpers.sampled_level_parity("C1B", circ, in_ct, lambda c: _eval(torch_cuda, ctx, c, in_ct, 1),
+                                        6, seed=24)
+    dec = np.stack([tfhe.decrypt(K, o) for o in outs])
+    assert np.array_equal(mi.from_bits(dec.T), _wrap(a + b, 16))
+
+
 def test_lr_formula_small(torch_cuda):
     """Closed-form regression (Alg. 7) on 4 data sets of m = 8 pairs, pair i
     encrypted by party i mod 2: sampled gates word for word against the
