@@ -92,6 +92,22 @@ def test_c8_gate_parity_eight_parties(torch_cuda):
     assert np.array_equal(got[idx], helpers.oracle_gates("C8", types, c1, c2, idx))
 
 
+def test_c8_adder_circuit(torch_cuda):
+    """A 4-bit adder through the circuit engine with 8 parties: operand a
+    from party 0, b from party 7, 16 pairs covering the range; every sum
+    decrypts to a + b (mod 16) and two sampled gates match the oracle."""
+    import paper_2205_05825_amd as mk
+    K, ctx = helpers.gpu_world("C8")
+    circ = mk.build_operator(mk.OP_ADD, 4)
+    a = np.arange(-8, 8)
+    b = np.roll(np.arange(-8, 8), 5)
+    in_ct = np.concatenate([_enc_operand(ctx, a, 4, 0, 31), _enc_operand(ctx, b, 4, 7, 32)])
+    outs = helpers.sampled_level_parity("C8", circ, in_ct, lambda c: _words(torch_cuda, ctx, c, in_ct)[0], 2,
+                                        seed=88)
+    dec = np.stack([ctx.decrypt(x) for x in outs])
+    assert np.array_equal(mi.from_bits(dec.T), _wrap(a + b, 4))
+
+
 def test_c3_multiplier_256_pairs(torch_cuda):
     """8-bit signed multiplier, 256 pairs in [-128, 127], 4 parties; a from
     party 0, b from party 1; one batch per bootstrapping level.  Six sampled
