@@ -347,7 +347,7 @@ def main():
                     help="operand pairs of the 16-bit adder, subtractor, multiplier and divider runs "
                          "(0: skip; minutes at 1024 pairs)")
     ap.add_argument("--batch-sizes", default="2048,4096",
-                    help="larger batches of the same gate mix to time (comma list; empty: skip)")
+                    help="larger batches of the same gate mix to time (comma list; 0 or empty: skip)")
     ap.add_argument("--party-gates", type=int, default=1024,
                     help="gates per batch of the 4- and 8-party runs (0: skip)")
     ap.add_argument("--formula-sets", type=int, default=0,
@@ -495,8 +495,9 @@ def main():
         res["operators_16bit"] = {op: operator_rate(torch, mk, ctx, args.all_operator_pairs, op, graph=op != "div")
                                   for op in OPERATORS}
         print("bench: 16-bit operators measured", file=sys.stderr, flush=True)
-    if head == mk.PATH_MFMA_I8 and args.batch_sizes:
-        res["batch_scaling"] = batch_scaling(torch, mk, ctx, [int(x) for x in args.batch_sizes.split(",")])
+    sizes = [int(x) for x in args.batch_sizes.split(",") if x.strip() and int(x) > 0]
+    if head == mk.PATH_MFMA_I8 and sizes:
+        res["batch_scaling"] = batch_scaling(torch, mk, ctx, sizes)
     if head == mk.PATH_MFMA_I8 and args.party_gates > 0:
         res["party_scaling"] = party_scaling(torch, mk, args.party_gates, (4, 8))
         res["party_scaling"]["2"] = {"gates_per_s": value, "ms_per_batch": sec * 1e3,

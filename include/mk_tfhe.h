@@ -323,7 +323,9 @@ int mk_get_profile(mk_ctx *ctx, double *ms, int64_t *launches, int reset);
  * (GT <= 4), 3 (GT <= 12), else the first shape whose row count divides N;
  * gemm2 shape 6 (GT <= 4), 5 (GT <= 12), else 3.
  *   mk_autotune   times every shape of both kernels on the scratch buffers of
- *                 a batch of `count` gates (synchronous on `stream`) and
+ *                 a batch of `count` gates (at most one rotation launch: larger
+ *                 counts tune the chunk size they run in; synchronous on
+ *                 `stream`) and
  *                 records the fastest for that batch size; ms (optional,
  *                 2 * MK_TILE_SHAPES floats) receives the average times,
  *                 gemm1 shapes first (0 for shapes that do not divide N/32).

@@ -606,7 +606,8 @@ __global__ __launch_bounds__(256, OCC) void mfma_gemm2_kernel(MfmaArgs a, int pa
 // block and key tiles start at l) and, with H = 2, over half of its K-blocks
 // (MR = 1 only), with a deeper prefetch.  The partial results, limbs already
 // combined, are summed through LDS by wave 0, which also does the
-// read-modify-write of the output.
+// read-modify-write of the output.  The launch bounds ask for two
+// workgroups per CU, which caps a wave at 256 registers.
 constexpr int kSplitD = 4;  // prefetch depth of the K-split GEMMs
 
 __device__ __forceinline__ Task decode_split(int GT, int RB) {
@@ -1329,6 +1330,7 @@ static int time_steps(mk_ctx *ctx, size_t count, int parts, const uint32_t *abar
 int autotune(mk_ctx *ctx, size_t count, hipStream_t s, int *v1_out, int *v2_out, float *ms_out) {
     const mk_params &P = ctx->p;
     DeviceKeys &D = ctx->dev;
+    count = std::min(count, rotation_chunk(P));  // larger batches run in chunks of this size
     hipEvent_t e0, e1;
     MK_HIP(hipEventCreate(&e0), "autotune event");
     if (hipEventCreate(&e1) != hipSuccess) {
