@@ -130,13 +130,14 @@ def _operator_want(op, a, b, bits=16):
     return [wrap(q), wrap(a - q * b)]
 
 
-def operator_rate(torch, mk, ctx, pairs, op="add", graph=True):
+def operator_rate(torch, mk, ctx, pairs, op="add", graph=True, sub=0):
     """16-bit two's-complement operator (adder 5k gates, Alg. 3; subtractor
     6k, Alg. 5; array multiplier; divider) on `pairs` operand pairs drawn
     from int16 (divisors non-zero), a from party 0 and b from party 1.  With
     `graph` the whole evaluation is captured as HIP graph pieces and the
     timed launch follows one warm-up launch; otherwise one eager call is
-    timed.  Every output is decrypted and checked."""
+    timed; with `sub` (< pairs) the pairs run eagerly in sub-batches of that
+    size, one progress line each.  Every output is decrypted and checked."""
     bits = 16
     circ = mk.build_operator(getattr(mk, OPERATORS[op]), bits)
     levels, live, width, _ = mk.circuit_stats(circ)
@@ -145,16 +146,19 @@ def operator_rate(torch, mk, ctx, pairs, op="add", graph=True):
     cols = np.concatenate([mi.to_bits(a, bits).T, mi.to_bits(b, bits).T])
     in_ct = np.stack([ctx.encrypt(0 if i < bits else 1, col, seed=400 + i) for i, col in enumerate(cols)])
     dev = torch.device("cuda:0")
-    inp = torch.from_numpy(np.ascontiguousarray(in_ct).view(np.int32)).to(dev)
-    out = torch.zeros((len(circ.outputs), pairs, words), dtype=torch.int32, device=dev)
+    sub = sub if 0 < sub < pairs else pairs
+    graph = graph and sub == pairs
     w = 1
     while w <= width:            # level batch sizes the autotuner sees first
-        ctx.autotune(min(w * pairs, 65536))
+        ctx.autotune(w * sub)
         w *= 2
     print("bench: %s16 autotuned; %s" % (op, "capturing the graph" if graph else "running"),
           file=sys.stderr, flush=True)
     pieces = 0
+    host_out = []
     if graph:
+        inp = torch.from_numpy(np.ascontiguousarray(in_ct).view(np.int32)).to(dev)
+        out = torch.zeros((len(circ.outputs), pairs, words), dtype=torch.int32, device=dev)
         g = ctx.circuit_graph(circ, inp, out)
         try:
             pieces = g.info()[2]
@@ -167,20 +171,28 @@ def operator_rate(torch, mk, ctx, pairs, op="add", graph=True):
             dt = time.perf_counter() - t0
         finally:
             g.close()
+        host_out.append(out.cpu().numpy().view(np.uint32))
     else:
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ctx.eval_circuit(circ, inp, out)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-    dec = np.stack([ctx.decrypt(x) for x in out.cpu().numpy().view(np.uint32)])
+        dt = 0.0
+        for s0 in range(0, pairs, sub):
+            inp = torch.from_numpy(np.ascontiguousarray(in_ct[:, s0:s0 + sub]).view(np.int32)).to(dev)
+            out = torch.zeros((len(circ.outputs), inp.shape[1], words), dtype=torch.int32, device=dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.eval_circuit(circ, inp, out)
+            torch.cuda.synchronize()
+            dt += time.perf_counter() - t0
+            host_out.append(out.cpu().numpy().view(np.uint32))
+            if sub < pairs:
+                print("bench: %s16 pairs %d..%d done" % (op, s0, s0 + inp.shape[1]), file=sys.stderr, flush=True)
+    dec = np.stack([ctx.decrypt(x) for x in np.concatenate(host_out, axis=1)])
     want = _operator_want(op, a, b, bits)
     per = len(circ.outputs) // len(want)
     for k, wv in enumerate(want):
         assert np.array_equal(mi.from_bits(dec[k * per:(k + 1) * per].T), wv), "%s16 outputs" % op
     return {"operator": op + "16", "pairs": pairs, "levels": levels, "gates_per_pair": live,
             "seconds": dt, "operators_per_s": pairs / dt, "gates_per_s": pairs * live / dt,
-            "graph": graph, "graph_pieces": pieces}
+            "graph": graph, "graph_pieces": pieces, "sub_batch": sub}
 
 
 def formula_lr(torch, mk, ctx, sets, m=64, frac=8):
@@ -348,6 +360,9 @@ def main():
                          "(0: skip; minutes at 1024 pairs)")
     ap.add_argument("--batch-sizes", default="2048,4096",
                     help="larger batches of the same gate mix to time (comma list; 0 or empty: skip)")
+    ap.add_argument("--operator-subbatch", type=int, default=0,
+                    help="with --all-operator-pairs: run the multiplier and divider eagerly in sub-batches "
+                         "of this many pairs (0: one batch)")
     ap.add_argument("--party-gates", type=int, default=1024,
                     help="gates per batch of the 4- and 8-party runs (0: skip)")
     ap.add_argument("--formula-sets", type=int, default=0,
@@ -492,7 +507,8 @@ def main():
         res["operators"] = operator_rate(torch, mk, ctx, args.operator_pairs)
         print("bench: operators measured", file=sys.stderr, flush=True)
     if head == mk.PATH_MFMA_I8 and args.all_operator_pairs > 0:
-        res["operators_16bit"] = {op: operator_rate(torch, mk, ctx, args.all_operator_pairs, op, graph=op != "div")
+        res["operators_16bit"] = {op: operator_rate(torch, mk, ctx, args.all_operator_pairs, op, graph=op != "div",
+                                                    sub=args.operator_subbatch if op in ("mul", "div") else 0)
                                   for op in OPERATORS}
         print("bench: 16-bit operators measured", file=sys.stderr, flush=True)
     sizes = [int(x) for x in args.batch_sizes.split(",") if x.strip() and int(x) > 0]
