@@ -387,7 +387,7 @@ def main():
         print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4}))
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on exactly one GPU (the path is per-GPU; "
+        print("bench.py: the path runs on exactly one GPU (its work is per GPU; "
               "--gpus %d is not supported)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 

@@ -9,7 +9,7 @@ the oracle's own implementation, written from that definition with numpy
 uint64 arithmetic; it is pinned against ``numpy.random.Philox`` (which is
 Philox4x64-10) in the tests.
 
-Stream addressing (a reading of this build; the paper is silent):
+Stream addressing (a reading made here; the paper is silent):
   key     = (seed, (party << 32) | obj)
   counter = (block, idx, 0, 0)
 Block ``b`` of stream (seed, party, obj, idx) yields four u64 words; the
