@@ -170,7 +170,10 @@ int mk_not(const mk_ctx *ctx, const uint32_t *in_dev, uint32_t *out_dev,
  * bits), sample extraction, multi-key key switching.  Batches larger than
  * one rotation launch takes (65536 gates, fewer when (k+1)*bk_ell*N*65536
  * reaches 2^31) run as consecutive chunks on `stream`.  `out` must not alias
- * the inputs.  Errors: MK_EINVAL (type >= MK_GATE_NOT, sizes),
+ * the inputs.  The gate types are device memory, so they are checked on
+ * the device: a type outside MK_GATE_NAND..MK_GATE_XNOR is evaluated as NAND
+ * and recorded in the context's status word, which mk_device_status then
+ * reports as MK_EINVAL.  Errors: MK_EINVAL (sizes, null pointers, path),
  * MK_ESTATE (mk_upload_eval_key not called), MK_ENOMEM, MK_EDEVICE. */
 int mk_bootstrap_gate(mk_ctx *ctx, const uint8_t *gate_types_dev,
                       const uint32_t *in1_dev, const uint32_t *in2_dev,
@@ -304,7 +307,8 @@ int mk_build_naive_gate(int type, mk_gate *gates, int32_t *n_gates, int32_t *n_w
  * for the events and returns accumulated milliseconds and launch counts for
  * MK_PROFILE_SLOTS slots: [0] pre-combination, [1] blind rotation (whole),
  * [2] extraction + key switching, [3] circuit bookkeeping, [4] MFMA stage-1
- * GEMM, [5] MFMA stage-2 GEMM, [6] rotate + decompose, [7] w decompose.
+ * GEMM or the persistent rotation kernel, [5] MFMA stage-2 GEMM, [6] rotate
+ * + decompose, [7] w decompose.
  * reset != 0 clears the accumulators.  Errors: MK_EINVAL. */
 #define MK_PROFILE_SLOTS 8
 int mk_set_profiling(mk_ctx *ctx, int level);
@@ -350,6 +354,35 @@ int mk_set_split(mk_ctx *ctx, size_t count, int parts);
 int mk_get_split(const mk_ctx *ctx, size_t count, int32_t *parts);
 int mk_get_tiles(const mk_ctx *ctx, size_t count, int32_t *gemm1_shape,
                  int32_t *gemm2_shape);
+
+/* Schedule of the int8-MFMA blind rotation (§3.1: a level's gates are
+ * independent, so all of them run together).  Both schedules give
+ * bit-identical results.
+ *   MK_ROT_STREAM      every CMux step is four stream-ordered kernels
+ *                      (rotate + decompose, stage-1 GEMM, w decompose,
+ *                      stage-2 GEMM), tile shapes as for mk_set_tiles.
+ *   MK_ROT_PERSISTENT  all k*n CMux steps of a batch in one launch: every
+ *                      32-gate tile is owned by one XCD, where a team of
+ *                      workgroups runs it, meeting at a barrier after each
+ *                      phase of a CMux step (rotate + decompose, stage 1,
+ *                      stage 2).  Needs N in {128, 256, 512, 1024, 2048}.
+ *   MK_ROT_AUTO        the persistent schedule for batches of at least four
+ *                      tiles per XCD (1024 gates on MI355X), where it is
+ *                      faster; stream-ordered kernels below (default).
+ * Errors: MK_EINVAL. */
+#define MK_ROT_AUTO -1
+#define MK_ROT_STREAM 0
+#define MK_ROT_PERSISTENT 1
+int mk_set_rotation(mk_ctx *ctx, int kind);
+
+/* Waits for `stream`, then reports and clears the context's device status
+ * word, which device entry points set when they meet a condition they can
+ * only detect on the GPU: MK_OK; MK_EINVAL if mk_bootstrap_gate met a gate
+ * type outside NAND..XNOR since the last call; MK_EDEVICE if a persistent
+ * rotation gave up waiting for another workgroup (its outputs are then
+ * invalid) or ran on an XCD the upload's probe did not see.  Errors:
+ * MK_EINVAL (null context), MK_ESTATE (key not uploaded), MK_EDEVICE. */
+int mk_device_status(mk_ctx *ctx, void *stream);
 
 /* Thread-local description of the last error on this thread. */
 const char *mk_last_error(void);

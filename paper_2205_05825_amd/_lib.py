@@ -32,6 +32,7 @@ _L = ctypes.CDLL(LIB_PATH)
 
 MK_OK, MK_EINVAL, MK_ENOMEM, MK_EDEVICE, MK_ESTATE, MK_EPARAM = 0, -1, -2, -3, -4, -5
 PATH_I32, PATH_MFMA_I8 = 0, 1
+ROT_AUTO, ROT_STREAM, ROT_PERSISTENT = -1, 0, 1
 TILE_SHAPES = 8
 NAND, AND, OR, NOR, XOR, XNOR, NOT = 0, 1, 2, 3, 4, 5, 6
 
@@ -96,6 +97,8 @@ _SIGS = {
                      ctypes.POINTER(ctypes.c_float)], _i),
     "mk_set_tiles": ([_vp, _i, _i], _i),
     "mk_get_tiles": ([_vp, _sz, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], _i),
+    "mk_set_rotation": ([_vp, _i], _i),
+    "mk_device_status": ([_vp, _vp], _i),
     "mk_set_profiling": ([_vp, _i], _i),
     "mk_get_profile": ([_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), _i], _i),
     "mk_last_error": ([], ctypes.c_char_p),
@@ -132,6 +135,43 @@ def _stream(stream):
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
+
+
+_WORD_DTYPES = None
+
+
+def _dev(t, name, ndim, dtypes=None):
+    """Checks that `t` is a contiguous tensor of rank `ndim` with 32-bit
+    words (or one of `dtypes`); where it lives is checked by _on_device once
+    all shapes are known.  A wrong element size, rank or a non-contiguous
+    view would make the kernels read or write out of bounds."""
+    global _WORD_DTYPES
+    if _WORD_DTYPES is None:
+        _WORD_DTYPES = tuple(d for d in (torch.int32, getattr(torch, "uint32", None)) if d is not None)
+    if not isinstance(t, torch.Tensor):
+        raise ValueError("%s: expected a torch tensor, got %s" % (name, type(t).__name__))
+    if t.dtype not in (dtypes or _WORD_DTYPES):
+        raise ValueError("%s: dtype %s not accepted" % (name, t.dtype))
+    if t.dim() != ndim:
+        raise ValueError("%s: expected %d dimensions, got shape %s" % (name, ndim, tuple(t.shape)))
+    if not t.is_contiguous():
+        raise ValueError("%s: tensor must be contiguous" % name)
+    return t
+
+
+def _on_device(**tensors):
+    """Every tensor is on the current HIP device (the library's device)."""
+    for name, t in tensors.items():
+        if not t.is_cuda:
+            raise ValueError("%s: expected a device tensor, got one on %s" % (name, t.device))
+        if t.device.index != torch.cuda.current_device():
+            raise ValueError("%s: tensor is on %s, the current device is cuda:%d"
+                             % (name, t.device, torch.cuda.current_device()))
+
+
+def _same(name, got, want):
+    if tuple(got) != tuple(want):
+        raise ValueError("%s: expected shape %s, got %s" % (name, tuple(want), tuple(got)))
 
 
 def _host(a, dtype):
@@ -245,6 +285,16 @@ class Context:
         _check(_L.mk_get_tiles(self._h, count, ctypes.byref(v1), ctypes.byref(v2)))
         return v1.value, v2.value
 
+    def set_rotation(self, kind: int = ROT_AUTO):
+        """Schedule of the MFMA rotation: ROT_STREAM (four kernels per CMux
+        step), ROT_PERSISTENT (one launch per rotation) or ROT_AUTO."""
+        _check(_L.mk_set_rotation(self._h, int(kind)))
+
+    def device_status(self, stream=None):
+        """Waits for the stream; raises MkError if a persistent rotation gave
+        up waiting (its outputs are then invalid)."""
+        _check(_L.mk_device_status(self._h, _stream(stream)))
+
     # ---- profiling ----
     def set_profiling(self, level: int):
         """0 off, 1 pipeline stages, 2 stages and each MFMA-rotation kernel."""
@@ -258,28 +308,62 @@ class Context:
         _check(_L.mk_get_profile(self._h, ms, ln, int(bool(reset))))
         return list(ms), list(ln)
 
-    # ---- device (torch tensors) ----
+    # ---- device (torch tensors; shapes checked before any call) ----
+    def _rows(self, t, name):
+        """[count, stride] ciphertext rows, stride >= kn+1."""
+        _dev(t, name, 2)
+        if t.shape[1] < self.params.lwe_words:
+            raise ValueError("%s: row stride %d < kn+1 = %d" % (name, t.shape[1], self.params.lwe_words))
+        return t
+
     def lwe_not(self, inp, out, stream=None):
+        self._rows(inp, "inp")
+        _same("out", self._rows(out, "out").shape, inp.shape)
+        _on_device(inp=inp, out=out)
         _check(_L.mk_not(self._h, _ptr(inp), _ptr(out), inp.shape[0], inp.shape[1],
                          _stream(stream)))
 
     def bootstrap_gate(self, types, in1, in2, out, path=PATH_MFMA_I8, stream=None):
-        assert in1.shape == in2.shape == out.shape and types.shape[0] == in1.shape[0]
+        self._rows(in1, "in1")
+        _same("in2", self._rows(in2, "in2").shape, in1.shape)
+        _same("out", self._rows(out, "out").shape, in1.shape)
+        _same("types", _dev(types, "types", 1, (torch.uint8,)).shape, (in1.shape[0],))
+        _on_device(types=types, in1=in1, in2=in2, out=out)
         _check(_L.mk_bootstrap_gate(self._h, _ptr(types), _ptr(in1), _ptr(in2), _ptr(out),
                                     in1.shape[0], in1.shape[1], path, _stream(stream)))
 
     def blind_rotate(self, abar, acc, max_steps=-1, path=PATH_MFMA_I8, stream=None):
+        P = self.params
+        _dev(abar, "abar", 2)
+        _same("abar", abar.shape, (abar.shape[0], P.lwe_words))
+        _same("acc", _dev(acc, "acc", 2).shape, (abar.shape[0], (P.k + 1) * P.N))
+        _on_device(abar=abar, acc=acc)
         _check(_L.mk_blind_rotate(self._h, _ptr(abar), _ptr(acc), abar.shape[0], max_steps,
                                   path, _stream(stream)))
 
     def extract_keyswitch(self, acc, out, path=PATH_MFMA_I8, stream=None):
+        P = self.params
+        _dev(acc, "acc", 2)
+        _same("acc", acc.shape, (acc.shape[0], (P.k + 1) * P.N))
+        _same("out rows", self._rows(out, "out").shape[:1], acc.shape[:1])
+        _on_device(acc=acc, out=out)
         _check(_L.mk_extract_keyswitch(self._h, _ptr(acc), _ptr(out), acc.shape[0],
                                        out.shape[1], path, _stream(stream)))
+
+    def _circuit_io(self, circuit, inp, out):
+        _dev(inp, "inp", 3)
+        _dev(out, "out", 3)
+        if inp.shape[2] < self.params.lwe_words:
+            raise ValueError("inp: row stride %d < kn+1 = %d" % (inp.shape[2], self.params.lwe_words))
+        _same("inp", inp.shape, (len(circuit.inputs), inp.shape[1], inp.shape[2]))
+        _same("out", out.shape, (len(circuit.outputs), inp.shape[1], inp.shape[2]))
+        _on_device(inp=inp, out=out)
 
     def circuit_graph(self, circuit: "Circuit", inp, out, path=PATH_MFMA_I8) -> "Graph":
         return Graph(self, circuit, inp, out, path)
 
     def eval_circuit(self, circuit: "Circuit", inp, out, path=PATH_MFMA_I8, stream=None):
+        self._circuit_io(circuit, inp, out)
         batch = inp.shape[1]
         _check(_L.mk_eval_circuit(self._h, ctypes.byref(circuit.c()), _ptr(inp), _ptr(out),
                                   batch, inp.shape[2], path, _stream(stream)))
@@ -290,6 +374,7 @@ class Graph:
     mk_circuit_graph_create); launch() replays it on the current inputs."""
 
     def __init__(self, ctx: "Context", circuit: "Circuit", inp, out, path=PATH_MFMA_I8):
+        ctx._circuit_io(circuit, inp, out)
         self._ctx = ctx                      # keeps the context alive
         self._bufs = (inp, out)              # the graph reads/writes these
         self._c = circuit.c()

@@ -99,7 +99,7 @@ void device_release(mk_ctx *ctx) {
     drain_events(ctx);
     DeviceKeys &D = ctx->dev;
     void *ptrs[] = {D.bk_ext, D.evk_ext, D.bk_win, D.evk_win, D.ks, D.ks_win, D.scratch, D.mfma_scratch,
-                    D.ks_scratch, D.circ_scratch};
+                    D.ks_scratch, D.circ_scratch, D.status};
     bool any = false;
     for (void *p : ptrs) any |= p != nullptr;
     if (any) {
@@ -115,7 +115,9 @@ void device_release(mk_ctx *ctx) {
     const auto tuned = D.tuned_tiles;
     const auto tuned_parts = D.tuned_parts;
     const int f0 = D.force_tiles[0], f1 = D.force_tiles[1];
+    const int rk = D.rot_kind;
     D = DeviceKeys();
+    D.rot_kind = rk;
     D.profiling = prof;
     D.tuned_tiles = tuned;
     D.tuned_parts = tuned_parts;
@@ -191,12 +193,14 @@ __global__ void precombine_kernel(const uint8_t *__restrict__ types,
                                   const uint32_t *__restrict__ in1,
                                   const uint32_t *__restrict__ in2, size_t stride,
                                   int words, int log2_2N, size_t total,
-                                  uint32_t *__restrict__ abar) {
+                                  uint32_t *__restrict__ abar, uint32_t *status) {
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= total) return;
     const size_t g = idx / words;
     const int w = (int)(idx - g * words);
-    const int t = types[g] < 6 ? types[g] : 0;  // out-of-range types read as NAND
+    // out-of-range types read as NAND and are reported through the status
+    const int t = types[g] < 6 ? types[g] : 0;
+    if (t != types[g] && w == 0) atomicOr(status, kStatusBadType);
     uint32_t x = (uint32_t)c_gate_s1[t] * in1[g * stride + w] +
                  (uint32_t)c_gate_s2[t] * in2[g * stride + w];
     if (w == 0) x += c_gate_const[t];
@@ -237,14 +241,17 @@ struct BrPlainArgs {
     uint32_t *acc_out;        // [count][(k+1)N]
 };
 
-__device__ __forceinline__ int mad24(int a, int b, int c) { return __mul24(a, b) + c; }
+// u * sext24(b) + c, wrapping mod 2^32: the 24-bit multiply gives the low 32
+// bits of the product, and the sums are unsigned so that their intended
+// wrap-around is defined.
+__device__ __forceinline__ uint32_t mad24(int a, int b, uint32_t c) { return (uint32_t)__mul24(a, b) + c; }
 
 // Accumulates the R outputs m0..m0+R-1 of sum_p u_p K'[m-p] for NK key
 // polynomials that share the digit polynomial u.
 template <int NK>
 __device__ __forceinline__ void toeplitz_mac(const int8_t *__restrict__ U,
                                              const uint32_t *const *Kx, int N, int m0,
-                                             int (&lo)[NK][kR], int (&hi)[NK][kR]) {
+                                             uint32_t (&lo)[NK][kR], uint32_t (&hi)[NK][kR]) {
     for (int p0 = 0; p0 < N; p0 += 8) {
         const int base = N + m0 - p0 - 8;
         int win[NK][16], winh[NK][16];
@@ -327,7 +334,7 @@ __global__ __launch_bounds__(512) void br_plain_kernel(BrPlainArgs a) {
         // 2. stage 1
         for (int u = tid; u < live * (N / kR); u += T) {
             const int j = u / (N / kR), m0 = (u - j * (N / kR)) * kR;
-            int lo[2][kR] = {}, hi[2][kR] = {};
+            uint32_t lo[2][kR] = {}, hi[2][kR] = {};
             for (int l = 0; l < ell; ++l) {
                 const uint32_t *Kx[2] = {bkbit + (size_t)(0 * ell + l) * 2 * N,
                                          a.evk_ext + (size_t)(j * ell + l) * 2 * N};
@@ -335,8 +342,8 @@ __global__ __launch_bounds__(512) void br_plain_kernel(BrPlainArgs a) {
             }
 #pragma unroll
             for (int r = 0; r < kR; ++r) {
-                acc[j * N + m0 + r] += (uint32_t)lo[0][r] + ((uint32_t)hi[0][r] << 24);
-                wpart[j * N + m0 + r] = (uint32_t)lo[1][r] + ((uint32_t)hi[1][r] << 24);
+                acc[j * N + m0 + r] += lo[0][r] + (hi[0][r] << 24);
+                wpart[j * N + m0 + r] = lo[1][r] + (hi[1][r] << 24);
             }
         }
         __syncthreads();
@@ -352,14 +359,14 @@ __global__ __launch_bounds__(512) void br_plain_kernel(BrPlainArgs a) {
         // 4. stage 2
         for (int u = tid; u < units2; u += T) {
             const int o = u / (N / kR), m0 = (u - o * (N / kR)) * kR;
-            int lo[1][kR] = {}, hi[1][kR] = {};
+            uint32_t lo[1][kR] = {}, hi[1][kR] = {};
             for (int l = 0; l < ell; ++l) {
                 const uint32_t *Kx[1] = {bkbit + (size_t)((1 + o) * ell + l) * 2 * N};
                 toeplitz_mac<1>(vdig + l * N, Kx, N, m0, lo, hi);
             }
             uint32_t *dst = acc + (o == 0 ? 0 : (1 + party)) * N + m0;
 #pragma unroll
-            for (int r = 0; r < kR; ++r) dst[r] += (uint32_t)lo[0][r] + ((uint32_t)hi[0][r] << 24);
+            for (int r = 0; r < kR; ++r) dst[r] += lo[0][r] + (hi[0][r] << 24);
         }
         __syncthreads();
     }
@@ -520,7 +527,7 @@ int run_gates(mk_ctx *ctx, const uint8_t *types, const uint32_t *in1, const uint
             StageTimer tm(ctx, 0, s);
             hipLaunchKernelGGL(precombine_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
                                types + c0, in1 + c0 * stride, in2 + c0 * stride, stride, (int)words, log2_2N,
-                               total, abar);
+                               total, abar, ctx->dev.status);
         }
         MK_HIP(hipGetLastError(), "precombine launch");
         if ((rc = run_blind_rotate(ctx, abar, acc, cnt, P.k * P.n, path, s)) ||

@@ -20,6 +20,11 @@ __host__ __device__ inline uint32_t decomp_offset(int ell) {
 
 int hip_fail(hipError_t e, const char *what);
 
+// Bits of the context's sticky device status word (DeviceKeys::status).
+constexpr uint32_t kStatusTimeout = 1u;   // a persistent rotation gave up waiting
+constexpr uint32_t kStatusNoXcd = 2u;     // it ran on an XCD the probe did not see
+constexpr uint32_t kStatusBadType = 4u;   // a gate type outside NAND..XNOR
+
 // Brackets a kernel launch with profiling events when enabled.
 struct StageTimer {
     StageTimer(mk_ctx *ctx, int stage, hipStream_t s);
@@ -39,6 +44,12 @@ int mfma_upload(mk_ctx *ctx, const std::vector<uint32_t> &evk, hipStream_t s);
 int launch_br_mfma(mk_ctx *ctx, const uint32_t *abar, uint32_t *acc, size_t count, int steps,
                    hipStream_t s);
 size_t mfma_scratch_need(const mk_params &P, size_t count);
+// Persistent rotation (mk_persist.hip).
+struct MfmaArgs;
+int persist_probe(mk_ctx *ctx, hipStream_t s);
+size_t persist_ctl_words(int GT);
+bool persist_supported(const mk_params &P);
+int launch_persist(mk_ctx *ctx, const MfmaArgs &m, int steps, uint32_t *ctl, hipStream_t s);
 // Key switching as an int8-MFMA GEMM (mk_keyswitch.hip).
 size_t ks_scratch_need(const mk_params &P, size_t count);
 int ks_mfma_upload(mk_ctx *ctx, hipStream_t s);

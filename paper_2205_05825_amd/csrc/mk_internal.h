@@ -67,6 +67,14 @@ struct DeviceKeys {
     void *capture = nullptr;
     void *aux_stream[2] = {nullptr, nullptr};
     void *aux_event[3] = {nullptr, nullptr, nullptr};
+    // Persistent rotation (mk_persist.hip): compute units, the XCDs found
+    // by the upload's probe (XCC_ID -> dense index), a sticky device status
+    // word, and the schedule choice (-1 automatic, 0 stream-ordered kernels,
+    // 1 persistent).
+    int num_cus = 0, num_xcd = 0;
+    int8_t xmap[16] = {};
+    uint32_t *status = nullptr;
+    int rot_kind = -1;
 };
 
 }  // namespace mk
