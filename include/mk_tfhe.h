@@ -50,6 +50,7 @@ extern "C" {
 #define MK_EDEVICE -3  /* a HIP call or kernel launch failed              */
 #define MK_ESTATE -4   /* keys missing / evaluation key not uploaded      */
 #define MK_EPARAM -5   /* parameters unsupported (see mk_setup)           */
+#define MK_EINTERNAL -6 /* an internal consistency check failed          */
 
 /* Gate types.  NAND..XNOR are bootstrapped (§4.1); NOT is free (Eq. (8)). */
 #define MK_GATE_NAND 0
@@ -222,12 +223,30 @@ int mk_graph_launch(mk_graph *graph, void *stream);
 int mk_graph_info(const mk_graph *graph, int32_t *n_levels, int64_t *gates, int32_t *pieces);
 int mk_graph_destroy(mk_graph *graph);
 
+/* Graph piece size: mk_circuit_graph_create cuts its capture after about
+ * `kernels` kernel nodes (default 1024).  Larger pieces mean fewer graph
+ * launches per replay.  Values outside [64, 4096] (4096 kernels per graph
+ * is the largest piece the test suite replays) are refused with MK_EINVAL;
+ * a capture whose piece would still exceed 4096 kernels fails the same
+ * way.  Takes effect for graphs created afterwards.  Host-only. */
+int mk_set_graph_piece(mk_ctx *ctx, int kernels);
+
 /* Host-side analysis of a netlist as mk_eval_circuit levels it: number of
  * bootstrapping levels, bootstrapped gates actually evaluated, widest level,
  * and wire slots needed per instance.  Any output pointer may be NULL.
  * Errors: MK_EINVAL for a malformed netlist. */
 int mk_circuit_stats(const mk_circuit *c, int32_t *n_levels, int64_t *live_gates,
                      int32_t *max_width, int32_t *slots);
+
+/* The wire-slot assignment behind mk_circuit_stats: for every wire w <
+ * c->n_wires, slot[w] is the slot (per instance) that holds its ciphertext
+ * (-1 for constants, NOT outputs and gates no output depends on) and
+ * level[w] its bootstrapping level (0 for inputs, -1 where slot is -1).
+ * A level's outputs never take a slot that a gate of that level or a later
+ * one still reads; the planner checks this itself (MK_EINTERNAL otherwise).
+ * Either pointer may be NULL; each array holds n_wires entries.
+ * Errors: MK_EINVAL for a malformed netlist. */
+int mk_circuit_slots(const mk_circuit *c, int32_t *slot, int32_t *level);
 
 /* Stage entry points (the same kernels as mk_bootstrap_gate, exposed so that
  * each step can be checked on its own).

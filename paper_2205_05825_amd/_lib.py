@@ -91,6 +91,9 @@ _SIGS = {
     "mk_circuit_stats": ([ctypes.POINTER(MkCircuit), ctypes.POINTER(ctypes.c_int32),
                           ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
                           ctypes.POINTER(ctypes.c_int32)], _i),
+    "mk_circuit_slots": ([ctypes.POINTER(MkCircuit), ctypes.POINTER(ctypes.c_int32),
+                          ctypes.POINTER(ctypes.c_int32)], _i),
+    "mk_set_graph_piece": ([_vp, _i], _i),
     "mk_set_split": ([_vp, _sz, _i], _i),
     "mk_get_split": ([_vp, _sz, ctypes.POINTER(ctypes.c_int32)], _i),
     "mk_autotune": ([_vp, _sz, _vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
@@ -285,6 +288,9 @@ class Context:
         _check(_L.mk_get_tiles(self._h, count, ctypes.byref(v1), ctypes.byref(v2)))
         return v1.value, v2.value
 
+    def set_graph_piece(self, kernels: int = 1024):
+        _check(_L.mk_set_graph_piece(self._h, int(kernels)))
+
     def set_rotation(self, kind: int = ROT_AUTO):
         """Schedule of the MFMA rotation: ROT_STREAM (four kernels per CMux
         step), ROT_PERSISTENT (one launch per rotation) or ROT_AUTO."""
@@ -466,3 +472,13 @@ def circuit_stats(c: "Circuit"):
     _check(_L.mk_circuit_stats(ctypes.byref(c.c()), ctypes.byref(nl), ctypes.byref(ng),
                                ctypes.byref(mw), ctypes.byref(sl)))
     return nl.value, ng.value, mw.value, sl.value
+
+
+def circuit_slots(c: "Circuit"):
+    """(slot, level) per wire as int32 arrays: the wire slot that holds each
+    ciphertext and its bootstrapping level (-1 for wires with no slot)."""
+    slot = np.empty(c.n_wires, np.int32)
+    level = np.empty(c.n_wires, np.int32)
+    _check(_L.mk_circuit_slots(ctypes.byref(c.c()), slot.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                               level.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+    return slot, level

@@ -115,9 +115,10 @@ void device_release(mk_ctx *ctx) {
     const auto tuned = D.tuned_tiles;
     const auto tuned_parts = D.tuned_parts;
     const int f0 = D.force_tiles[0], f1 = D.force_tiles[1];
-    const int rk = D.rot_kind;
+    const int rk = D.rot_kind, gp = D.graph_piece;
     D = DeviceKeys();
     D.rot_kind = rk;
+    D.graph_piece = gp;
     D.profiling = prof;
     D.tuned_tiles = tuned;
     D.tuned_parts = tuned_parts;

@@ -279,6 +279,19 @@ int plan_circuit(const mk_circuit *c, CircuitPlan &P) {
         live.push_back({st, n, last});
     }
     P.total_slots = top;
+    // Check the assignment: when level l writes a slot, the wire held there
+    // before must have no reader at level l or later (a wide level runs in
+    // chunks, so its gates read their inputs while its outputs are written).
+    std::vector<int> holder(top, -1);
+    for (int i = 0; i < c->n_inputs; ++i) holder[P.slot[c->inputs[i]]] = c->inputs[i];
+    for (int l = 1; l <= L; ++l) {
+        for (int gi : P.levels[l]) {
+            const int h = holder[P.slot[c->gates[gi].out]];
+            if (h >= 0 && lastuse[h] >= l)
+                return fail(MK_EINTERNAL, "mk_eval_circuit: wire slot reused while still read (planner bug)");
+        }
+        for (int gi : P.levels[l]) holder[P.slot[c->gates[gi].out]] = c->gates[gi].out;
+    }
     return MK_OK;
 }
 
@@ -395,6 +408,11 @@ __global__ void copy_words_kernel(const uint32_t *__restrict__ src, uint32_t *__
     if (idx < n) dst[idx] = src[idx];
 }
 
+// Kernels of one chunk of a level outside the stepwise rotation (which
+// reports its own): pre-combination, accumulator set-up and copies of the
+// persistent rotation, extraction and key switching, with some margin.
+constexpr int kChunkKernels = 8;
+
 // Device work of one evaluation, kernels only (so that it can be captured
 // into a graph): inputs into their wire slots, every level's
 // pre-combination, blind rotation and key switching, then the outputs.
@@ -429,7 +447,8 @@ int enqueue_run(mk_ctx *ctx, const CircuitRun &R, uint32_t *gate_scratch, const 
             if (hipGetLastError() != hipSuccess) return fail(MK_EDEVICE, "circuit precombine launch failed");
             uint32_t *dst = R.wires + ((size_t)P.level_base[l] * batch + c0) * stride;
             if ((rc = run_blind_rotate(ctx, abar, acc, cnt, Pm.k * Pm.n, R.path, s)) ||
-                (rc = run_key_switch(ctx, acc, dst, cnt, stride, R.path, s)))
+                (rc = run_key_switch(ctx, acc, dst, cnt, stride, R.path, s)) ||
+                (rc = capture_checkpoint(ctx, s, kChunkKernels)))
                 return rc;
         }
     }
@@ -444,23 +463,28 @@ int enqueue_run(mk_ctx *ctx, const CircuitRun &R, uint32_t *gate_scratch, const 
     return MK_OK;
 }
 
-// A capture is cut into consecutive graphs of about kGraphKernels kernel
-// nodes (one rotation step is 4): each piece stays far from the node counts
-// at which building one graph for a whole operator failed (one level of a
-// 2-party Table 7 rotation alone is 4480 kernels), and pieces replayed in
-// order on one stream are equivalent to the whole sequence.
-constexpr int kGraphKernels = 1024;
+// A capture is cut into consecutive graphs of about `piece` kernel nodes
+// (default 1024; one stream-ordered rotation step is 4): each piece stays
+// far from the node counts at which building one graph for a whole operator
+// failed (one level of a 2-party Table 7 rotation alone is 4480 kernels),
+// and pieces replayed in order on one stream are equivalent to the whole
+// sequence.  No piece may exceed kGraphMaxKernels, the largest one tested.
+constexpr int kGraphMinKernels = 64;
+constexpr int kGraphMaxKernels = 4096;
 
 struct CaptureState {
     mk_graph *g;
     int kernels;
+    int piece;
 };
 
 int capture_checkpoint(mk_ctx *ctx, hipStream_t s, int kernels) {
     CaptureState *cs = (CaptureState *)ctx->dev.capture;
     if (!cs) return MK_OK;
     cs->kernels += kernels;
-    if (cs->kernels < kGraphKernels) return MK_OK;
+    if (cs->kernels > kGraphMaxKernels)
+        return fail(MK_EINVAL, "graph capture: a piece exceeds 4096 kernels (untested size)");
+    if (cs->kernels < cs->piece) return MK_OK;
     hipGraph_t piece = nullptr;
     if (hipStreamEndCapture(s, &piece) != hipSuccess || !piece)
         return fail(MK_EDEVICE, "graph capture: ending a piece failed");
@@ -502,6 +526,25 @@ int mk_circuit_stats(const mk_circuit *c, int32_t *n_levels, int64_t *live_gates
     if (live_gates) *live_gates = P.live_gates;
     if (max_width) *max_width = P.max_width;
     if (slots) *slots = P.total_slots;
+    return MK_OK;
+}
+
+int mk_set_graph_piece(mk_ctx *ctx, int kernels) {
+    if (!ctx || kernels < kGraphMinKernels || kernels > kGraphMaxKernels)
+        return fail(MK_EINVAL, "mk_set_graph_piece: kernels outside [64, 4096]");
+    ctx->dev.graph_piece = kernels;
+    return MK_OK;
+}
+
+int mk_circuit_slots(const mk_circuit *c, int32_t *slot, int32_t *level) {
+    CircuitPlan P;
+    int rc = plan_circuit(c, P);
+    if (rc) return rc;
+    for (int w = 0; w < c->n_wires; ++w) {
+        const bool live = P.slot[w] >= 0;
+        if (slot) slot[w] = P.slot[w];
+        if (level) level[w] = live ? P.level[w] : -1;
+    }
     return MK_OK;
 }
 
@@ -583,7 +626,7 @@ int mk_circuit_graph_create(mk_ctx *ctx, const mk_circuit *c, const uint32_t *in
     D.mfma_scratch = g->buf[2]; D.mfma_scratch_bytes = g->bytes[2];
     D.ks_scratch = g->buf[3]; D.ks_scratch_bytes = g->bytes[3];
     D.profiling = 0;
-    CaptureState state{g, 0};
+    CaptureState state{g, 0, D.graph_piece};
     D.capture = &state;
     rc = MK_OK;
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {

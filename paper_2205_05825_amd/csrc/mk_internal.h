@@ -65,6 +65,7 @@ struct DeviceKeys {
     // Graph capture in progress (mk_circuit_graph_create): the capture is cut
     // into consecutive graphs of at most about kGraphSteps CMux steps.
     void *capture = nullptr;
+    int graph_piece = 1024;   // kernels per captured piece (mk_set_graph_piece)
     void *aux_stream[2] = {nullptr, nullptr};
     void *aux_event[3] = {nullptr, nullptr, nullptr};
     // Persistent rotation (mk_persist.hip): compute units, the XCDs found

@@ -64,7 +64,7 @@ constexpr int kCtlPerTeam = 64;    // one barrier counter per team (256 B apart)
 constexpr int kHdrAbort = 0, kHdrReg = 16;  // kHdrReg + x: workgroups registered on XCD x
 constexpr int kRGates = 4;         // gates per R unit
 constexpr int kMaxRUnits = 4;      // R units held in LDS at once
-constexpr int kCombineBytes = 2 * 4 * 4 * 64 * 16;   // limb-combination buffer
+constexpr int kLimbTileBytes = 4 * 4 * 64 * 16;     // one row tile's four limbs in LDS
 
 // Row block, prefetch depth and workgroups per compute unit of the
 // contraction for N = 32 NB (the rings of the seamless schedule must divide
@@ -220,36 +220,60 @@ __device__ __forceinline__ void load_old_coherent(__amdgpu_buffer_rsrc_t r, size
     }
 }
 
-// Combines the four waves' limb sums of w (rows of row block rb, i.e. the
-// coefficients of K-blocks rb MR ..) and writes their ell digits into V:
-// after the limb sum a thread holds the 4 consecutive coefficients
-// 32 kb + 8 t + 4 h .. + 3 of its lane's gate, which are bytes 8 (t & 1) +
-// 4 h .. + 3 of fragment piece (kb, lane 32 (t >> 1) + g) of each plane.
+// Limb combination in one LDS round: every wave writes all MR of its limb
+// tiles, shifted by 8 t (limb t weighs 2^(8t)), then after one barrier wave
+// t sums quad t (registers 4t..4t+3, i.e. words 8t..8t+3 of its lane's row
+// within each 32-row tile) over the four limbs.  `red` holds MR x 16 KB.
 template <int MR>
-__device__ __forceinline__ void combine_to_v(const MfmaArgs &a, int tile, int rb, int t, int lane,
-                                             const v16i (&acc)[MR][1], uint4 *red) {
+__device__ __forceinline__ void limb_sums(const v16i (&acc)[MR][1], int t, int lane, uint4 *red,
+                                          uint4 (&sum)[MR]) {
+    const uint32_t sh = 8u * (uint32_t)t;
+#pragma unroll
+    for (int i = 0; i < MR; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            red[((i * 4 + t) * 4 + q) * 64 + lane] =
+                make_uint4((uint32_t)acc[i][0][4 * q + 0] << sh, (uint32_t)acc[i][0][4 * q + 1] << sh,
+                           (uint32_t)acc[i][0][4 * q + 2] << sh, (uint32_t)acc[i][0][4 * q + 3] << sh);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MR; ++i) {
+        uint4 v = red[((i * 4 + 0) * 4 + t) * 64 + lane];
+#pragma unroll
+        for (int l = 1; l < 4; ++l) {
+            const uint4 x = red[((i * 4 + l) * 4 + t) * 64 + lane];
+            v.x += x.x;
+            v.y += x.y;
+            v.z += x.z;
+            v.w += x.w;
+        }
+        sum[i] = v;
+    }
+}
+
+// Row tile i of the task (rows 32 (rb MR + i) ..): the thread's 4 words
+// 8 t + 4 h .. + 3 of its lane's gate go to `base` (gate stride given).
+template <int MR>
+__device__ __forceinline__ void store_sums(uint32_t *base, size_t gate_stride, int tile, int rb, int t, int lane,
+                                           const uint4 (&sum)[MR]) {
+    const int g = tile * 32 + (lane & 31);
+#pragma unroll
+    for (int i = 0; i < MR; ++i)
+        *reinterpret_cast<uint4 *>(base + (size_t)g * gate_stride + 32 * (rb * MR + i) + 8 * t + 4 * (lane >> 5)) =
+            sum[i];
+}
+
+// The ell digits of w into V: a thread's 4 consecutive coefficients
+// 32 kb + 8 t + 4 h .. + 3 of its lane's gate are bytes 8 (t & 1) + 4 h ..
+// + 3 of fragment piece (kb, lane 32 (t >> 1) + g) of each digit plane.
+template <int MR>
+__device__ __forceinline__ void store_v_digits(const MfmaArgs &a, int tile, int rb, int t, int lane,
+                                               const uint4 (&sum)[MR]) {
     const int NB = a.N / 32, GT = a.GP / 32;
     const int h = lane >> 5, g = lane & 31;
 #pragma unroll
     for (int i = 0; i < MR; ++i) {
-        uint4 *buf = red + (i & 1) * 4 * 4 * 64;
-        const uint32_t sh = 8u * (uint32_t)t;
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            buf[(t * 4 + q) * 64 + lane] =
-                make_uint4((uint32_t)acc[i][0][4 * q + 0] << sh, (uint32_t)acc[i][0][4 * q + 1] << sh,
-                           (uint32_t)acc[i][0][4 * q + 2] << sh, (uint32_t)acc[i][0][4 * q + 3] << sh);
-        __syncthreads();
-        uint4 sum = buf[t * 64 + lane];
-#pragma unroll
-        for (int s = 1; s < 4; ++s) {
-            const uint4 v = buf[(s * 4 + t) * 64 + lane];
-            sum.x += v.x;
-            sum.y += v.y;
-            sum.z += v.z;
-            sum.w += v.w;
-        }
-        const uint32_t y[4] = {sum.x + a.offset, sum.y + a.offset, sum.z + a.offset, sum.w + a.offset};
+        const uint32_t y[4] = {sum[i].x + a.offset, sum[i].y + a.offset, sum[i].z + a.offset, sum[i].w + a.offset};
         const int kb = rb * MR + i;
         int8_t *dst = a.V + ((size_t)tile * NB + kb) * kTileBytes + (32 * (t >> 1) + g) * 16 + 8 * (t & 1) + 4 * h;
 #pragma unroll
@@ -303,23 +327,17 @@ __device__ __forceinline__ void task_gemm(const PersistArgs &p, int kind, int j_
     // the tile's rows of the read-modify-write output (w has none)
     const __amdgpu_buffer_rsrc_t rbase = __builtin_amdgcn_make_buffer_rsrc(
         (void *)(base + (size_t)t * 32 * gate_stride), (short)0, (int)(32 * gate_stride * 4), kBufWord3);
+    // the old output values are loaded before the contraction's own loads
+    // and turned into limb seeds (registers only) once those are in flight
     const bool seed = kind != 1 && (w == 0 || w == 3);
+    if (seed) load_old_coherent<MR>(rbase, gate_stride, rb, lane, acc);
     slide_gemm<MR, NB, PersistCfg<NB>::D, kCoherent>(o, w, lane, acc, [&]() {
-        if (seed) {
-            load_old_coherent<MR>(rbase, gate_stride, rb, lane, acc);
-            seed_old<MR, 1>(w, acc);
-        }
+        if (seed) seed_old<MR, 1>(w, acc);
     });
-    if (kind == 1) {
-        combine_to_v<MR>(a, t, rb, w, lane, acc, red);
-    } else {
-        Task tk;
-        tk.unit = 0;
-        tk.rb = rb;
-        tk.gt0 = t;
-        tk.nc_valid = 1;
-        combine_store<MR, 1>(base, gate_stride, tk, w, lane, acc, red);
-    }
+    uint4 sum[MR];
+    limb_sums<MR>(acc, w, lane, red, sum);
+    if (kind == 1) store_v_digits<MR>(a, t, rb, w, lane, sum);
+    else store_sums<MR>(base, gate_stride, t, rb, w, lane, sum);
     __syncthreads();   // red is reused by the next task
 }
 
@@ -434,7 +452,8 @@ template <int NB>
 static int launch_nb(mk_ctx *ctx, PersistArgs &pa, hipStream_t s) {
     const DeviceKeys &D = ctx->dev;
     auto kern = persist_rotation_kernel<NB>;
-    const size_t lds = std::max<size_t>((size_t)kMaxRUnits * kRGates * NB * 32 * 4, (size_t)kCombineBytes);
+    const size_t lds = std::max<size_t>((size_t)kMaxRUnits * kRGates * NB * 32 * 4,
+                                        (size_t)PersistCfg<NB>::MR * kLimbTileBytes);
     if (lds > 65536)
         MK_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
                "persistent rotation LDS attribute");

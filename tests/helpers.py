@@ -72,20 +72,53 @@ def assert_same_keys(name):
             assert np.array_equal(got[f], getattr(ref, f)), (name, i, f)
 
 
-def oracle_gates(name, types, c1, c2, idx=None, workers=8):
-    """Oracle outputs of bootstrapped gates ``idx`` (threads: the oracle's C
-    product releases the GIL)."""
-    from concurrent.futures import ThreadPoolExecutor
-    K = oracle_keys(name)
-    evk = K.evaluation_key()
-    idx = range(len(types)) if idx is None else idx
-    W = K.params.lwe_words
+_POOL = None
 
-    def one(g):
-        return tfhe.bootstrapped_gate(K, int(types[g]), c1[g, :W], c2[g, :W], evk)
 
-    with ThreadPoolExecutor(max_workers=workers) as ex:
-        return np.stack(list(ex.map(one, idx)))
+def oracle_pool():
+    """Process pool for oracle work (the oracle's numpy steps hold the GIL,
+    so threads do not run gates in parallel).  The forkserver start method
+    gives workers that never inherited this process's GPU state; each worker
+    regenerates a parameter set's keys from its seed on first use."""
+    global _POOL
+    if _POOL is None:
+        import multiprocessing as mp
+        import os
+        from concurrent.futures import ProcessPoolExecutor
+        _POOL = ProcessPoolExecutor(max_workers=max(1, min(16, os.cpu_count() or 1)),
+                                    mp_context=mp.get_context("forkserver"))
+    return _POOL
+
+
+@functools.lru_cache(maxsize=None)
+def _evk(name):
+    return oracle_keys(name).evaluation_key()
+
+
+def _oracle_gate_job(name, t, c1, c2):
+    return tfhe.bootstrapped_gate(oracle_keys(name), int(t), c1, c2, _evk(name))
+
+
+def _oracle_rotation_job(name, abar, steps):
+    return tfhe.blind_rotate(oracle_keys(name), np.asarray(abar, np.int64), _evk(name),
+                             max_steps=None if steps < 0 else steps)
+
+
+def oracle_gates(name, types, c1, c2, idx=None):
+    """Oracle outputs of bootstrapped gates ``idx`` (all by default),
+    computed in the oracle process pool."""
+    W = getattr(OP, name).lwe_words
+    idx = list(range(len(types))) if idx is None else list(idx)
+    jobs = [oracle_pool().submit(_oracle_gate_job, name, int(types[g]), np.ascontiguousarray(c1[g, :W]),
+                                 np.ascontiguousarray(c2[g, :W])) for g in idx]
+    return np.stack([j.result() for j in jobs])
+
+
+def oracle_rotations(name, abar, steps=-1):
+    """Oracle blind rotations of the rows of abar (first `steps` CMux steps,
+    all if negative), in the oracle process pool."""
+    jobs = [oracle_pool().submit(_oracle_rotation_job, name, np.ascontiguousarray(row), steps) for row in abar]
+    return np.stack([np.asarray(j.result()) for j in jobs])
 
 
 def gpu_world(name):
@@ -99,17 +132,19 @@ def gpu_world(name):
     return oracle_keys(name), ctx
 
 
-def oracle_circuit(name, nl, in_ct, workers=8):
+def oracle_circuit(name, nl, in_ct):
     """Oracle gate-by-gate evaluation of netlist nl on in_ct[n_in, B, words],
-    one instance per thread."""
-    from concurrent.futures import ThreadPoolExecutor
-    from oracle import circuits as C
-    K = oracle_keys(name)
-    W = K.params.lwe_words
+    one instance per pool worker."""
+    W = getattr(OP, name).lwe_words
     Bn = in_ct.shape[1]
-    with ThreadPoolExecutor(max_workers=workers) as ex:
-        outs = list(ex.map(lambda b: C.eval_encrypted(nl, K, in_ct[:, b:b + 1, :W]), range(Bn)))
-    return np.concatenate(outs, axis=1)
+    jobs = [oracle_pool().submit(_oracle_circuit_job, name, nl, np.ascontiguousarray(in_ct[:, b:b + 1, :W]))
+            for b in range(Bn)]
+    return np.concatenate([j.result() for j in jobs], axis=1)
+
+
+def _oracle_circuit_job(name, nl, in_ct):
+    from oracle import circuits as C
+    return C.eval_encrypted(nl, oracle_keys(name), in_ct)
 
 
 def encrypt_operands(K, values, bits, party, seed):
@@ -119,25 +154,72 @@ def encrypt_operands(K, values, bits, party, seed):
     return np.stack([tfhe.encrypt(K, party, col, seed=seed + 1000 * i) for i, col in enumerate(cols)])
 
 
-def sampled_level_parity(name, circ, in_ct, evaluate, samples, seed, workers=8):
-    """Per-gate parity inside a full-size circuit run.
+def live_levels(circ):
+    """Bootstrapping level of every live bootstrapped gate of a netlist, as
+    the engine levels it: NOT gates are free (a NOT's output has its
+    input's level), inputs and constants are level 0, a bootstrapped gate is
+    one above its deepest input; gates no output depends on are dropped.
+    Returns {gate index: level}."""
+    NOT = 6
+    gates = [tuple(int(x) for x in g) for g in circ.gates]
+    base = {}       # wire -> producing bootstrapped gate's output wire (or None)
+    level = {}
+    for w in list(circ.inputs) + [0, 1]:
+        base[int(w)] = None
+        level[int(w)] = 0
+    for t, a, b, o in gates:
+        if t == NOT:
+            base[o] = base[a]
+            level[o] = level[a]
+        else:
+            base[o] = o
+            level[o] = 1 + max(level[a], level[b])
+    needed = set()
+    for w in circ.outputs:
+        if base[int(w)] is not None:
+            needed.add(base[int(w)])
+    for t, a, b, o in reversed(gates):
+        if t == NOT or o not in needed:
+            continue
+        for w in (a, b):
+            if base[w] is not None:
+                needed.add(base[w])
+    return {gi: level[g[3]] for gi, g in enumerate(gates) if g[0] != NOT and g[3] in needed}
 
-    `samples` (gate, instance) items are drawn (seeded) from the bootstrapped
-    gates; the circuit is evaluated on the GPU with those gates' input and
-    output wires appended to its outputs (evaluate(circuit) -> u32[n_out, B,
-    words]); then the oracle recomputes each sampled gate from the GPU's own
-    input ciphertexts (constants as trivial ciphertexts, inputs as given) and
-    the result must equal the GPU's output word for word.  By induction over
-    the levels this checks every level at these shapes.  Returns the GPU
-    outputs of the original circuit's outputs."""
-    from concurrent.futures import ThreadPoolExecutor
+
+def sampled_level_parity(name, circ, in_ct, evaluate, seed, max_levels=64):
+    """Per-gate oracle parity inside a full-size circuit run, at every level.
+
+    One (gate, instance) item is drawn (seeded) from the live bootstrapped
+    gates of every bootstrapping level; circuits deeper than max_levels get
+    every s-th level from a seeded offset (s = ceil(levels / max_levels)),
+    plus the first and the last.  The circuit is evaluated twice on the GPU
+    (evaluate(circuit) -> u32[n_out, B, words]): as given, and with the
+    sampled gates' input and output wires appended to its outputs.  The
+    sampled gates are live already, so both runs evaluate the same gates in
+    the same levels and only the wire slots differ: the original outputs
+    must equal the first outputs of the extended run word for word.  Then
+    the oracle recomputes each sampled gate from the GPU's own input
+    ciphertexts (constants as trivial ciphertexts, inputs as given) and the
+    result must equal the GPU's output word for word; with a sample at every
+    level this checks each level given the one before.  Returns the
+    original run's outputs and the list of (gate, instance) items."""
     import paper_2205_05825_amd as mk
     K = oracle_keys(name)
     P = K.params
     W = P.lwe_words
     rng = np.random.default_rng(seed)
-    boot = [i for i, g in enumerate(circ.gates) if g[0] != mk.NOT]
-    picks = [(int(rng.choice(boot)), int(rng.integers(0, in_ct.shape[1]))) for _ in range(samples)]
+    lv = live_levels(circ)
+    by_level = {}
+    for gi, l in lv.items():
+        by_level.setdefault(l, []).append(gi)
+    levels = sorted(by_level)
+    if len(levels) > max_levels:
+        step = -(-len(levels) // max_levels)
+        off = int(rng.integers(0, step))
+        keep = set(levels[off::step]) | {levels[0], levels[-1]}
+        levels = [l for l in levels if l in keep]
+    picks = [(int(rng.choice(by_level[l])), int(rng.integers(0, in_ct.shape[1]))) for l in levels]
     extra = []
     for gi, _ in picks:
         _, a, b, o = (int(x) for x in circ.gates[gi])
@@ -145,9 +227,10 @@ def sampled_level_parity(name, circ, in_ct, evaluate, samples, seed, workers=8):
     n0 = len(circ.outputs)
     ext = mk.Circuit(circ.n_wires, circ.inputs, np.concatenate([circ.outputs, np.array(extra, np.int32)]),
                      circ.gates)
+    plain = evaluate(circ)
     got = evaluate(ext)
+    assert np.array_equal(plain, got[:n0]), "exposing internal wires changed the outputs"
     input_pos = {int(w): i for i, w in enumerate(circ.inputs)}
-    evk = K.evaluation_key()
 
     def wire_ct(w, row, inst):
         if w in (0, 1):
@@ -156,14 +239,13 @@ def sampled_level_parity(name, circ, in_ct, evaluate, samples, seed, workers=8):
             return np.asarray(in_ct[input_pos[w], inst, :W], np.uint32)
         return got[row, inst, :W]
 
-    def check(k):
-        gi, inst = picks[k]
+    jobs = []
+    for k, (gi, inst) in enumerate(picks):
         t, a, b, _ = (int(x) for x in circ.gates[gi])
         base = n0 + 3 * k
-        c1, c2 = wire_ct(a, base, inst), wire_ct(b, base + 1, inst)
-        return np.array_equal(tfhe.bootstrapped_gate(K, t, c1, c2, evk), got[base + 2, inst, :W])
-
-    with ThreadPoolExecutor(max_workers=workers) as ex:
-        ok = list(ex.map(check, range(len(picks))))
-    assert all(ok), [p for p, f in zip(picks, ok) if not f]
-    return got[:n0]
+        jobs.append(oracle_pool().submit(_oracle_gate_job, name, t, np.ascontiguousarray(wire_ct(a, base, inst)),
+                                         np.ascontiguousarray(wire_ct(b, base + 1, inst))))
+    bad = [p for k, (p, j) in enumerate(zip(picks, jobs))
+           if not np.array_equal(j.result(), got[n0 + 3 * k + 2, p[1], :W])]
+    assert not bad, bad
+    return plain, picks

@@ -124,8 +124,7 @@ def test_wide_level_runs_in_chunks(torch_cuda):
     a, b = mi.operand_pairs(pairs, 8, seed=21)
     in_ct = np.concatenate([helpers.encrypt_operands(K, a, 8, 0, 2100),
                             helpers.encrypt_operands(K, b, 8, 1, 2200)])
-    outs = helpers.sampled_level_parity("C1B", circ, in_ct, lambda c: _eval(torch_cuda, ctx, c, in_ct, 1),
-                                        6, seed=23)
+    outs, _ = helpers.sampled_level_parity("C1B", circ, in_ct, lambda c: _eval(torch_cuda, ctx, c, in_ct, 1), seed=23)
     dec = np.stack([tfhe.decrypt(K, o) for o in outs])
     assert np.array_equal(mi.from_bits(dec.T), a * b)
 
@@ -145,8 +144,7 @@ def test_chunked_level_reading_reused_slots(torch_cuda):
     a, b = mi.operand_pairs(pairs, 16, seed=22)
     in_ct = np.concatenate([helpers.encrypt_operands(K, a, 16, 0, 2300),
                             helpers.encrypt_operands(K, b, 16, 1, 2400)])
-    outs = helpers.sampled_level_parity("C1B", circ, in_ct, lambda c: _eval(torch_cuda, ctx, c, in_ct, 1),
-                                        6, seed=24)
+    outs, _ = helpers.sampled_level_parity("C1B", circ, in_ct, lambda c: _eval(torch_cuda, ctx, c, in_ct, 1), seed=24)
     dec = np.stack([tfhe.decrypt(K, o) for o in outs])
     assert np.array_equal(mi.from_bits(dec.T), _wrap(a + b, 16))
 
@@ -163,8 +161,7 @@ def test_lr_formula_small(torch_cuda):
     bits = lr.formula_input_bits(x, y)
     owner = lr.formula_input_owner(m, 2)
     in_ct = np.stack([tfhe.encrypt(K, int(owner[i]), bits[i], seed=700 + i) for i in range(len(bits))])
-    outs = helpers.sampled_level_parity("C1B", circ, in_ct, lambda c: _eval(torch_cuda, ctx, c, in_ct, 1),
-                                        8, seed=71)
+    outs, _ = helpers.sampled_level_parity("C1B", circ, in_ct, lambda c: _eval(torch_cuda, ctx, c, in_ct, 1), seed=71)
     dec = np.stack([tfhe.decrypt(K, o) for o in outs])
     got = list(zip(mi.from_bits(dec[:16].T).tolist(), mi.from_bits(dec[16:].T).tolist()))
     assert got == [lr.formula_replica(a, b) for a, b in zip(x, y)]

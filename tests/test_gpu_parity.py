@@ -7,6 +7,7 @@ import mk_inputs as mi
 from oracle import params as OP
 from oracle import tfhe
 from tests import helpers
+from tests.golden.make_oracle_digests import digest, load as golden_digests, rotation_inputs
 
 pytestmark = pytest.mark.gpu
 
@@ -141,19 +142,56 @@ def test_extract_keyswitch_shapes(torch_cuda, name, cnt):
         _keyswitch_case(torch_cuda, name, cnt, path, 50 + cnt)
 
 
-@pytest.mark.parametrize("path", PATHS)
-def test_c2_batch_1024(torch_cuda, path):
-    """The 1024-gate mixed workload: all outputs decrypt to the plaintext
-    gate, and sampled outputs equal the oracle's word for word."""
+# (path, rotation schedule) pairs: the i32 path, and the MFMA path with the
+# stream-ordered and the persistent blind rotation
+SCHEDULES = [(0, -1), (1, 0), (1, 1)]
+
+
+def _with_rotation(ctx, kind, fn):
+    ctx.set_rotation(kind)
+    try:
+        return fn()
+    finally:
+        ctx.set_rotation(-1)
+
+
+@pytest.mark.parametrize("path,rot", SCHEDULES)
+def test_c2_batch_1024(torch_cuda, path, rot):
+    """The 1024-gate mixed workload at the Table 7 shape: every output word
+    of every gate equals the oracle's (SHA-256 digests of the oracle's rows
+    written by tests/golden/make_oracle_digests.py), every output decrypts
+    to the plaintext gate, and two gates are recomputed by the oracle live."""
     K, ctx = helpers.gpu_world("C2")
     types, m1, m2 = mi.gate_batch(1024, seed=2)
     c1, c2 = _workload(K, types, m1, m2, seed=200)
-    got = _gates_on_gpu(torch_cuda, ctx, types, c1, c2, path)
+    got = _with_rotation(ctx, rot, lambda: _gates_on_gpu(torch_cuda, ctx, types, c1, c2, path))
+    ctx.device_status()
     want = [mi.plain_gate(int(t), int(a), int(b)) for t, a, b in zip(types, m1, m2)]
     assert tfhe.decrypt(K, got).tolist() == want
-    idx = [0, 1, 511, 1023] + list(np.random.default_rng(6).choice(1024, 4, replace=False))
-    ref = helpers.oracle_gates("C2", types, c1, c2, idx)
-    assert np.array_equal(got[idx], ref)
+    dig = golden_digests()
+    bad = [g for g in range(1024) if digest(got[g]) != dig[("gate", g)]]
+    assert not bad, bad[:20]
+    idx = [int(i) for i in np.random.default_rng(6 + path + rot).choice(1024, 2, replace=False)]
+    assert np.array_equal(got[idx], helpers.oracle_gates("C2", types, c1, c2, idx))
+
+
+@pytest.mark.parametrize("path,rot", SCHEDULES)
+def test_c2_full_rotation(torch_cuda, path, rot):
+    """All k n = 1120 CMux steps of 8 gates at the Table 7 shape, every
+    accumulator word against the oracle's digests."""
+    K, ctx = helpers.gpu_world("C2")
+    P = K.params
+    abar = rotation_inputs()
+    d = torch_cuda.device("cuda:0")
+    ta = torch_cuda.from_numpy(abar.view(np.int32)).to(d)
+    acc = torch_cuda.zeros((len(abar), (P.k + 1) * P.N), dtype=torch_cuda.int32, device=d)
+    _with_rotation(ctx, rot, lambda: ctx.blind_rotate(ta, acc, path=path))
+    torch_cuda.cuda.synchronize()
+    ctx.device_status()
+    got = acc.cpu().numpy().view(np.uint32)
+    dig = golden_digests()
+    bad = [g for g in range(len(abar)) if digest(got[g]) != dig[("rot", g)]]
+    assert not bad, bad
 
 
 @pytest.mark.parametrize("path", PATHS)

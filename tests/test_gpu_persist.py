@@ -1,0 +1,125 @@
+"""The persistent blind rotation (one launch for all CMux steps, XCD-local
+teams of workgroups) against the oracle and against the stream-ordered
+schedule, word for word, through the C ABI (needs an MI355X)."""
+import numpy as np
+import pytest
+
+import mk_inputs as mi
+from oracle import tfhe
+from paper_2205_05825_amd import MkError
+from tests import helpers
+
+pytestmark = pytest.mark.gpu
+
+STREAM, PERSISTENT = 0, 1
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+def _gates(torch, ctx, types, c1, c2, rot):
+    d = torch.device("cuda:0")
+    t = torch.from_numpy(np.ascontiguousarray(types, np.uint8)).to(d)
+    a = torch.from_numpy(np.ascontiguousarray(c1).view(np.int32)).to(d)
+    b = torch.from_numpy(np.ascontiguousarray(c2).view(np.int32)).to(d)
+    out = torch.full_like(a, -1)
+    ctx.set_rotation(rot)
+    try:
+        ctx.bootstrap_gate(t, a, b, out, path=1)
+    finally:
+        ctx.set_rotation(-1)
+    torch.cuda.synchronize()
+    ctx.device_status()
+    return out.cpu().numpy().view(np.uint32)
+
+
+def _rotate(torch, ctx, abar, steps, rot):
+    P = ctx.params
+    d = torch.device("cuda:0")
+    ta = torch.from_numpy(np.ascontiguousarray(abar).view(np.int32)).to(d)
+    acc = torch.zeros((len(abar), (P.k + 1) * P.N), dtype=torch.int32, device=d)
+    ctx.set_rotation(rot)
+    try:
+        ctx.blind_rotate(ta, acc, max_steps=steps, path=1)
+    finally:
+        ctx.set_rotation(-1)
+    torch.cuda.synchronize()
+    ctx.device_status()
+    return acc.cpu().numpy().view(np.uint32)
+
+
+def _workload(K, cnt, seed):
+    types, m1, m2 = mi.gate_batch(cnt, seed=seed)
+    c1 = tfhe.encrypt(K, 0, m1, seed=seed + 1)
+    c2 = tfhe.encrypt(K, K.params.k - 1, m2, seed=seed + 2)
+    return types, m1, m2, c1, c2
+
+
+@pytest.mark.parametrize("name,cnt", [("C1B", 70), ("C1S", 45), ("C1B4", 97), ("C1B", 1)])
+def test_gates_every_word(torch_cuda, name, cnt):
+    """Whole gates with the persistent rotation forced: every output word
+    equals the oracle's (N = 256 and N = 128 rings, k = 2 and k = 4 parties,
+    ragged gate tiles, a single gate) and decrypts to the plaintext gate
+    (the C1B noise levels make every gate decrypt; C1's do not)."""
+    K, ctx = helpers.gpu_world(name)
+    types, m1, m2, c1, c2 = _workload(K, cnt, 60 + cnt)
+    got = _gates(torch_cuda, ctx, types, c1, c2, PERSISTENT)
+    assert np.array_equal(got, helpers.oracle_gates(name, types, c1, c2))
+    want = [mi.plain_gate(int(t), int(a), int(b)) for t, a, b in zip(types, m1, m2)]
+    assert tfhe.decrypt(K, got).tolist() == want
+
+
+@pytest.mark.parametrize("name,cnt,steps", [("C2", 200, 600), ("C2", 1061, 40), ("C3", 97, 600),
+                                            ("C8", 40, 1200)])
+def test_partial_rotation_matches_stream(torch_cuda, name, cnt, steps):
+    """Partial blind rotations that cross party boundaries (live slots grow
+    from 2 to k + 1): the persistent and the stream-ordered schedules give
+    the same words, and sampled gates equal the oracle's.  1061 gates leave
+    a ragged last tile and more tiles than the XCDs divide evenly."""
+    K, ctx = helpers.gpu_world(name)
+    P = K.params
+    abar = np.random.default_rng(cnt + steps).integers(0, 2 * P.N, (cnt, P.lwe_words)).astype(np.uint32)
+    abar[0, :] = 0                      # every step skipped
+    abar[1, ::3] = 0
+    per = _rotate(torch_cuda, ctx, abar, steps, PERSISTENT)
+    strm = _rotate(torch_cuda, ctx, abar, steps, STREAM)
+    assert np.array_equal(per, strm)
+    idx = [0, 1, cnt - 1]
+    ref = helpers.oracle_rotations(name, abar[idx], steps)
+    assert np.array_equal(per[idx], ref.reshape(len(idx), -1))
+
+
+def test_batch_sizes_around_the_team_grid(torch_cuda):
+    """Gate counts around multiples of the tile (32 gates) and of the XCD
+    count: persistent and stream-ordered outputs are identical and decrypt."""
+    K, ctx = helpers.gpu_world("C1B")
+    types, m1, m2, c1, c2 = _workload(K, 1100, 90)
+    want = np.array([mi.plain_gate(int(t), int(a), int(b)) for t, a, b in zip(types, m1, m2)])
+    for cnt in (31, 33, 255, 257, 1100):
+        a = _gates(torch_cuda, ctx, types[:cnt], c1[:cnt], c2[:cnt], PERSISTENT)
+        b = _gates(torch_cuda, ctx, types[:cnt], c1[:cnt], c2[:cnt], STREAM)
+        assert np.array_equal(a, b), cnt
+        assert np.array_equal(tfhe.decrypt(K, a), want[:cnt]), cnt
+
+
+def test_status_reports_bad_gate_types(torch_cuda):
+    """A gate type outside NAND..XNOR is evaluated as NAND and flagged in the
+    device status word; reading the status clears it."""
+    K, ctx = helpers.gpu_world("C1")
+    types, m1, m2, c1, c2 = _workload(K, 4, 70)
+    types = np.array([mi.NAND, 9, mi.AND, mi.XOR], np.uint8)
+    d = torch_cuda.device("cuda:0")
+    out = torch_cuda.full((4, c1.shape[1]), -1, dtype=torch_cuda.int32, device=d)
+    ctx.bootstrap_gate(torch_cuda.from_numpy(types).to(d), torch_cuda.from_numpy(c1.view(np.int32)).to(d),
+                       torch_cuda.from_numpy(c2.view(np.int32)).to(d), out, path=1)
+    with pytest.raises(MkError):
+        ctx.device_status()
+    ctx.device_status()                 # cleared by the read
+    got = out.cpu().numpy().view(np.uint32)
+    as_nand = types.copy()
+    as_nand[1] = mi.NAND
+    assert np.array_equal(got, helpers.oracle_gates("C1", as_nand, c1, c2))
