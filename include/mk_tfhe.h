@@ -181,6 +181,26 @@ int mk_bootstrap_gate(mk_ctx *ctx, const uint8_t *gate_types_dev,
                       uint32_t *out_dev, size_t count, size_t stride, int path,
                       void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation as mk_bootstrap_gate, bit for bit, with every scratch buffer
+ * in one fixed block of MK_NOALLOC_SCRATCH_BYTES per GPU (a static device
+ * array that each GPU the library runs on holds until the process ends).
+ * The call allocates and frees nothing; it does not split a batch over
+ * streams and records no profiling events.  The block holds about 1000
+ * gates at the Table 7 shape on MK_PATH_MFMA_I8 (about 61 KB per gate,
+ * counted in 32-gate tiles); larger batches are refused with MK_EINVAL
+ * before any work (split them).  Every call on one GPU, from any context,
+ * uses the same block and leaves its contents behind: calls that may
+ * overlap on one GPU (different streams, threads or contexts) race and
+ * must be ordered by the caller.  Arguments, layouts and the other errors
+ * are those of mk_bootstrap_gate. */
+#define MK_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int mk_bootstrap_gate_noalloc(mk_ctx *ctx, const uint8_t *gate_types_dev,
+                              const uint32_t *in1_dev, const uint32_t *in2_dev,
+                              uint32_t *out_dev, size_t count, size_t stride,
+                              int path, void *stream);
+
 /* Evaluates `batch` independent instances of a netlist (Algs. 3-6).
  * in_dev: [n_inputs][batch][stride] words, out_dev: [n_outputs][batch]
  * [stride] words (device memory).  NOT gates and the constant wires are

@@ -67,6 +67,7 @@ _SIGS = {
     "mk_trivial": ([_vp, _vp, _sz, _vp, _sz], _i),
     "mk_not": ([_vp, _vp, _vp, _sz, _sz, _vp], _i),
     "mk_bootstrap_gate": ([_vp, _vp, _vp, _vp, _vp, _sz, _sz, _i, _vp], _i),
+    "mk_bootstrap_gate_noalloc": ([_vp, _vp, _vp, _vp, _vp, _sz, _sz, _i, _vp], _i),
     "mk_eval_circuit": ([_vp, ctypes.POINTER(MkCircuit), _vp, _vp, _sz, _sz, _i, _vp], _i),
     "mk_circuit_graph_create": ([_vp, ctypes.POINTER(MkCircuit), _vp, _vp, _sz, _sz, _i,
                                  ctypes.POINTER(_vp)], _i),
@@ -329,14 +330,17 @@ class Context:
         _check(_L.mk_not(self._h, _ptr(inp), _ptr(out), inp.shape[0], inp.shape[1],
                          _stream(stream)))
 
-    def bootstrap_gate(self, types, in1, in2, out, path=PATH_MFMA_I8, stream=None):
+    def bootstrap_gate(self, types, in1, in2, out, path=PATH_MFMA_I8, stream=None, noalloc=False):
+        """Bootstrapped gates out[g] = types[g](in1[g], in2[g]); with
+        `noalloc` through mk_bootstrap_gate_noalloc (fixed scratch block)."""
         self._rows(in1, "in1")
         _same("in2", self._rows(in2, "in2").shape, in1.shape)
         _same("out", self._rows(out, "out").shape, in1.shape)
         _same("types", _dev(types, "types", 1, (torch.uint8,)).shape, (in1.shape[0],))
         _on_device(types=types, in1=in1, in2=in2, out=out)
-        _check(_L.mk_bootstrap_gate(self._h, _ptr(types), _ptr(in1), _ptr(in2), _ptr(out),
-                                    in1.shape[0], in1.shape[1], path, _stream(stream)))
+        fn = _L.mk_bootstrap_gate_noalloc if noalloc else _L.mk_bootstrap_gate
+        _check(fn(self._h, _ptr(types), _ptr(in1), _ptr(in2), _ptr(out), in1.shape[0], in1.shape[1], path,
+                  _stream(stream)))
 
     def blind_rotate(self, abar, acc, max_steps=-1, path=PATH_MFMA_I8, stream=None):
         P = self.params

@@ -69,6 +69,7 @@ static void drain_events(mk_ctx *ctx) {
 int ensure_scratch(mk_ctx *ctx, size_t bytes) {
     DeviceKeys &D = ctx->dev;
     if (D.scratch_bytes >= bytes) return MK_OK;
+    if (D.fixed_scratch) return fail(MK_EINTERNAL, "fixed scratch block too small (gate buffers)");
     if (D.scratch) {
         MK_HIP(hipDeviceSynchronize(), "scratch sync");
         (void)hipFree(D.scratch);

@@ -58,6 +58,9 @@ int launch_ks_mfma(mk_ctx *ctx, const uint32_t *acc, uint32_t *out, size_t count
 // During a graph capture: ends the current graph after enough kernels and
 // begins the next one on the same stream (mk_engine.hip).
 int capture_checkpoint(mk_ctx *ctx, hipStream_t s, int kernels);
+// The whole gate pipeline on `count` gates (mk_device.hip).
+int run_gates(mk_ctx *ctx, const uint8_t *types, const uint32_t *in1, const uint32_t *in2,
+              uint32_t *out, size_t count, size_t stride, int path, hipStream_t s);
 // Sample extraction + key switching on the given path (mk_device.hip).
 int run_key_switch(mk_ctx *ctx, const uint32_t *acc, uint32_t *out, size_t count, size_t stride, int path,
                    hipStream_t s);

@@ -53,6 +53,9 @@ struct DeviceKeys {
     size_t mfma_scratch_bytes = 0;
     void *ks_scratch = nullptr;     // rounded coefficients of the MFMA key switch
     size_t ks_scratch_bytes = 0;
+    // Set while the scratch pointers above point into a caller-fixed block
+    // (the allocation-free entry point): nothing is grown or split then.
+    bool fixed_scratch = false;
     void *circ_scratch = nullptr;   // circuit wire buffer and descriptors
     size_t circ_scratch_bytes = 0;
     // GEMM tile shapes of the MFMA rotation: autotuned per batch size (in

@@ -300,6 +300,7 @@ int launch_ks_mfma(mk_ctx *ctx, const uint32_t *acc, uint32_t *out, size_t count
         return fail(MK_EINVAL, "int8-MFMA key switching: batch too large for one launch (split it)");
     const size_t need = ks_scratch_need(P, count);
     if (D.ks_scratch_bytes < need) {
+        if (D.fixed_scratch) return fail(MK_EINTERNAL, "fixed scratch block too small (key switching)");
         if (D.ks_scratch) {
             MK_HIP(hipStreamSynchronize(s), "ks scratch sync");
             (void)hipFree(D.ks_scratch);

@@ -617,7 +617,7 @@ static Split split_for(const mk_ctx *ctx, size_t count) {
     Split sp{1, {count, 0}, {0, 0}};
     const int GT = (int)((count + 31) / 32);
     auto it = ctx->dev.tuned_parts.find(GT);
-    if (it != ctx->dev.tuned_parts.end() && it->second == 2 && GT >= 2) {
+    if (!ctx->dev.fixed_scratch && it != ctx->dev.tuned_parts.end() && it->second == 2 && GT >= 2) {
         sp.parts = 2;
         sp.cnt[0] = (size_t)((GT + 1) / 2) * 32;
         sp.cnt[1] = count - sp.cnt[0];
@@ -642,6 +642,7 @@ static int prepare(mk_ctx *ctx, const uint32_t *abar, const Split &sp, hipStream
     }
     DeviceKeys &D = ctx->dev;
     if (D.mfma_scratch_bytes < need) {
+        if (D.fixed_scratch) return fail(MK_EINTERNAL, "fixed scratch block too small (MFMA rotation)");
         if (D.mfma_scratch) {
             MK_HIP(hipDeviceSynchronize(), "mfma scratch sync");
             (void)hipFree(D.mfma_scratch);
