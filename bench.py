@@ -1,6 +1,6 @@
 """Benchmark: bootstrapped multi-key gates per second on one MI355X.
 
-Workload (default): a batch of 1024 independent bootstrapped gates, types
+Headline workload: a batch of 1024 independent bootstrapped gates, types
 uniform over AND/OR/NOR/XOR/XNOR/NAND, uniform input bits, 2 parties (input 1
 encrypted by party 0, input 2 by party 1), n=560, N=1024, gadget base 2^8 with
 ell=3, key-switching base 2^2 with t=8 (Table 7 shape with B = 2^8).  One
@@ -9,9 +9,14 @@ switch, blind rotation (k*n = 1120 hybrid-product CMux steps), sample
 extraction and multi-key key switching.  Ciphertexts and keys are resident in
 HBM before timing starts; key generation and upload are excluded.
 
-Prints one JSON line.  The headline value is the int8-MFMA path; the plain
-32-bit integer path is timed on the same batch and reported beside it, and
-the two outputs are checked to be bit-identical before timing.
+The default run also times, with every output decrypted and checked: the
+plain 32-bit integer path on the same batch (outputs bit-identical to the
+MFMA path), the 4-party 8-bit multiplier on 256 pairs, the 16-bit adder,
+subtractor (4096 pairs each), multiplier and divider (256 pairs each),
+one encrypted gradient-descent step of linear regression (m=64, d=4), larger
+batches, 4 and 8 parties, the scheme's gates against NAND-composed ones, and
+the CPU oracle on bounded samples (C2 and the 8-gate C1 workload, one core
+and all cores).  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -39,8 +44,17 @@ PEAK_INT8_OPS = 5.0e15          # MI355X dense int8 MFMA
 PEAK_VALU_TORUS_MACS = 256 * 64 * 2.4e9 / 2
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "mfma_gemm1_c2_1024gates_hbm_traffic.md")
-MFMA_SOURCE = os.path.join(ROOT, "paper_2205_05825_amd", "csrc", "mk_mfma.hip")
+CSRC = os.path.join(ROOT, "paper_2205_05825_amd", "csrc")
+# HBM traffic summaries (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)
+# and the sources each kernel is built from: a summary counts only while the
+# sha256 of those sources matches the one it records.
+TRAFFIC = {
+    "gemm1": (os.path.join(ROOT, "profiles", "mfma_gemm1_c2_1024gates_hbm_traffic.md"),
+              [os.path.join(CSRC, "mk_mfma.hip")]),
+    "persist": (os.path.join(ROOT, "profiles", "persist_rotation_c2_1024gates_hbm_traffic.md"),
+                [os.path.join(CSRC, "mk_persist.hip"), os.path.join(CSRC, "mk_mfma_core.h")]),
+}
+PERSIST_KERNEL = "persist_rotation_kernel<32>"
 
 
 # Stage-1 GEMM instantiation run for each tile shape (the shape table of
@@ -51,15 +65,23 @@ GEMM1_KERNEL = {0: "mfma_gemm1_limb_kernel<8, 1, 2>", 1: "mfma_gemm1_limb_kernel
                 6: "mfma_gemm1_split_kernel<1, 1>", 7: "mfma_gemm1_split_kernel<1, 2>"}
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3
-    FETCH_SIZE/WRITE_SIZE summary, or None when that kernel was not measured
-    or its source changed since the counters were taken."""
+def sources_sha(paths):
     import hashlib
+    h = hashlib.sha256()
+    for p in paths:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(which, kernel):
+    """HBM bytes per launch of `kernel` from its committed traffic summary,
+    or None when that kernel was not measured or its sources changed since
+    the counters were taken."""
     import re
+    path, srcs = TRAFFIC[which]
     try:
-        text = open(TRAFFIC_PROFILE).read()
-        src = hashlib.sha256(open(MFMA_SOURCE, "rb").read()).hexdigest()
+        text = open(path).read()
+        src = sources_sha(srcs)
     except OSError:
         return None
     m = re.search(r"HBM bytes per launch \[%s\]: (\d+)" % re.escape(kernel), text)
@@ -75,6 +97,16 @@ def macs_per_gate(p):
     return p["k"] * p["n"] * (2 * p["k"] + 4) * p["bk_ell"] * p["N"] ** 2
 
 
+def executed_int8_ops_per_gate(p):
+    """Int8 operations the MFMA rotation executes per gate: in party i's
+    steps only the accumulator slots j < L = min(k+1, i+2) can be non-zero,
+    so a step runs 2 L ell products in stage 1 (c'_j and the w sum) and
+    2 ell in stage 2, each N^2 Torus32 multiply-adds of 4 int8 limb
+    products, 2 operations per multiply-add."""
+    k, n, ell, N = p["k"], p["n"], p["bk_ell"], p["N"]
+    return sum(n * (2 * min(k + 1, i + 2) * ell + 2 * ell) for i in range(k)) * 8 * N * N
+
+
 # ------------------------------------------------------- CPU baseline ----
 _CPU = {}
 
@@ -85,30 +117,56 @@ def _cpu_gate(g):
     return tfhe.bootstrapped_gate(K, int(types[g]), c1[g], c2[g], evk)
 
 
+def _cpu_rate(ctx, K, types, m1, m2, c1, c2, sample, cores):
+    """Gates/s of the oracle over `sample` on `cores` processes (1 = in this
+    process), with every output decrypted against its truth table."""
+    from oracle import tfhe
+    _CPU["state"] = (K, K.evaluation_key(), types, c1, c2)
+    t0 = time.perf_counter()
+    if cores == 1:
+        outs = [_cpu_gate(g) for g in sample]
+    else:
+        with ctx.Pool(cores) as pool:
+            outs = pool.map(_cpu_gate, sample, chunksize=1)
+    dt = time.perf_counter() - t0
+    want = [mi.plain_gate(int(types[g]), int(m1[g]), int(m2[g])) for g in sample]
+    ok = tfhe.decrypt(K, np.stack(outs)).tolist() == want
+    return len(sample) / dt, dt, ok
+
+
 def cpu_baseline(gates_per_core: int):
-    """The oracle, as it stands, on a bounded sample of the same workload,
-    one process per host core (fork before any GPU use)."""
+    """The oracle, as it stands, on bounded samples of the workloads, one
+    process per host core for the all-core rates (fork before any GPU use):
+    the C2 gate mix (the headline workload: gates_per_core gates per core
+    on all cores, and one gate on one core) and the 8-gate C1 truth-table
+    workload (all 8 gates on one core and on all cores)."""
     import multiprocessing as mp
 
     from oracle import params as OP
     from oracle import tfhe
+    cores = min(os.cpu_count() or 1, 16)
+    ctx = mp.get_context("fork")
     K = tfhe.generate(OP.C2, SEED)
     types, m1, m2 = mi.gate_batch(BATCH, seed=SEED)
     c1 = tfhe.encrypt(K, 0, m1, seed=200)
     c2 = tfhe.encrypt(K, 1, m2, seed=201)
-    _CPU["state"] = (K, K.evaluation_key(), types, c1, c2)
-    cores = min(os.cpu_count() or 1, 16)
-    sample = list(range(cores * gates_per_core))
-    ctx = mp.get_context("fork")
-    t0 = time.perf_counter()
-    with ctx.Pool(cores) as pool:
-        outs = pool.map(_cpu_gate, sample, chunksize=1)
-    dt = time.perf_counter() - t0
-    want = [mi.plain_gate(int(types[g]), int(m1[g]), int(m2[g])) for g in sample]
-    ok = tfhe.decrypt(K, np.stack(outs)).tolist() == want
-    return {"value": len(sample) / dt, "unit": "gates/s", "cores": cores, "kind": "oracle",
-            "sample": "%d of the %d workload gates (%d per core), %.1f s wall, decrypt %s"
-                      % (len(sample), BATCH, gates_per_core, dt, "ok" if ok else "FAILED")}
+    all_rate, all_dt, all_ok = _cpu_rate(ctx, K, types, m1, m2, c1, c2, list(range(cores * gates_per_core)), cores)
+    one_rate, one_dt, one_ok = _cpu_rate(ctx, K, types, m1, m2, c1, c2, list(range(4)), 1)
+    K1 = tfhe.generate(OP.C1, 0)
+    t1, a1, b1 = mi.truth_table(gates=(mi.XOR, mi.NAND))
+    e1, e2 = tfhe.encrypt(K1, 0, a1, seed=0), tfhe.encrypt(K1, 1, b1, seed=1)
+    c1_one = _cpu_rate(ctx, K1, t1, a1, b1, e1, e2, list(range(len(t1))), 1)
+    c1_all = _cpu_rate(ctx, K1, t1, a1, b1, e1, e2, list(range(len(t1))), min(cores, len(t1)))
+    return {"value": all_rate, "unit": "gates/s", "cores": cores, "kind": "oracle",
+            "sample": "%d of the %d workload gates (%d per core) on %d cores, %.1f s wall, decrypt %s"
+                      % (cores * gates_per_core, BATCH, gates_per_core, cores, all_dt, "ok" if all_ok else "FAILED"),
+            "one_core": {"value": one_rate, "unit": "gates/s", "cores": 1,
+                         "sample": "gates 0..3 of the workload, %.1f s, decrypt %s" % (one_dt, "ok" if one_ok else "FAILED")},
+            "c1_truth_table": {"gates": len(t1), "one_core_gates_per_s": c1_one[0],
+                               "all_core_gates_per_s": c1_all[0], "all_core_processes": min(cores, len(t1)),
+                               "decrypts_to_truth_table": bool(c1_one[2] and c1_all[2]),
+                               "note": "C1 (k=2, n=64, N=256, ell=2, toy noise): 4 XOR + 4 NAND on every "
+                                       "input pair"}}
 
 
 # ---------------------------------------------------------------- GPU ----
@@ -130,21 +188,22 @@ def _operator_want(op, a, b, bits=16):
     return [wrap(q), wrap(a - q * b)]
 
 
-def operator_rate(torch, mk, ctx, pairs, op="add", graph=True, sub=0):
-    """16-bit two's-complement operator (adder 5k gates, Alg. 3; subtractor
-    6k, Alg. 5; array multiplier; divider) on `pairs` operand pairs drawn
-    from int16 (divisors non-zero), a from party 0 and b from party 1.  With
-    `graph` the whole evaluation is captured as HIP graph pieces and the
-    timed launch follows one warm-up launch; otherwise one eager call is
-    timed; with `sub` (< pairs) the pairs run eagerly in sub-batches of that
-    size, one progress line each.  Every output is decrypted and checked."""
-    bits = 16
+def operator_rate(torch, mk, ctx, pairs, op="add", bits=16, graph=True, sub=0, parties=(0, 1), seed=4):
+    """`bits`-bit two's-complement operator (adder 5k gates, Alg. 3;
+    subtractor 6k, Alg. 5; array multiplier; divider) on `pairs` operand
+    pairs drawn uniformly (divisors non-zero), a encrypted by parties[0] and
+    b by parties[1].  With `graph` the whole evaluation is captured as HIP
+    graph pieces and the timed launch follows one warm-up launch; otherwise
+    one eager call is timed; with `sub` (< pairs) the pairs run eagerly in
+    sub-batches of that size, one progress line each.  Every output is
+    decrypted and checked against plain integer arithmetic."""
     circ = mk.build_operator(getattr(mk, OPERATORS[op]), bits)
     levels, live, width, _ = mk.circuit_stats(circ)
-    a, b = mi.operand_pairs(pairs, bits, seed=4, nonzero_second=op == "div")
-    words = C2["k"] * C2["n"] + 1
+    a, b = mi.operand_pairs(pairs, bits, seed=seed, nonzero_second=op == "div")
+    words = ctx.params.lwe_words
     cols = np.concatenate([mi.to_bits(a, bits).T, mi.to_bits(b, bits).T])
-    in_ct = np.stack([ctx.encrypt(0 if i < bits else 1, col, seed=400 + i) for i, col in enumerate(cols)])
+    in_ct = np.stack([ctx.encrypt(parties[0] if i < bits else parties[1], col, seed=400 + i)
+                      for i, col in enumerate(cols)])
     dev = torch.device("cuda:0")
     sub = sub if 0 < sub < pairs else pairs
     graph = graph and sub == pairs
@@ -152,7 +211,8 @@ def operator_rate(torch, mk, ctx, pairs, op="add", graph=True, sub=0):
     while w <= width:            # level batch sizes the autotuner sees first
         ctx.autotune(w * sub)
         w *= 2
-    print("bench: %s16 autotuned; %s" % (op, "capturing the graph" if graph else "running"),
+    name = "%s%d" % (op, bits)
+    print("bench: %s autotuned; %s" % (name, "capturing the graph" if graph else "running"),
           file=sys.stderr, flush=True)
     pieces = 0
     host_out = []
@@ -184,15 +244,103 @@ def operator_rate(torch, mk, ctx, pairs, op="add", graph=True, sub=0):
             dt += time.perf_counter() - t0
             host_out.append(out.cpu().numpy().view(np.uint32))
             if sub < pairs:
-                print("bench: %s16 pairs %d..%d done" % (op, s0, s0 + inp.shape[1]), file=sys.stderr, flush=True)
+                print("bench: %s pairs %d..%d done" % (name, s0, s0 + inp.shape[1]), file=sys.stderr, flush=True)
+    ctx.device_status()
     dec = np.stack([ctx.decrypt(x) for x in np.concatenate(host_out, axis=1)])
     want = _operator_want(op, a, b, bits)
     per = len(circ.outputs) // len(want)
     for k, wv in enumerate(want):
-        assert np.array_equal(mi.from_bits(dec[k * per:(k + 1) * per].T), wv), "%s16 outputs" % op
-    return {"operator": op + "16", "pairs": pairs, "levels": levels, "gates_per_pair": live,
+        assert np.array_equal(mi.from_bits(dec[k * per:(k + 1) * per].T), wv), "%s outputs" % name
+    print("bench: %s on %d pairs: %.1f s, every output correct" % (name, pairs, dt), file=sys.stderr, flush=True)
+    return {"operator": name, "pairs": pairs, "levels": levels, "gates_per_pair": live,
             "seconds": dt, "operators_per_s": pairs / dt, "gates_per_s": pairs * live / dt,
-            "graph": graph, "graph_pieces": pieces, "sub_batch": sub}
+            "graph": graph, "graph_pieces": pieces, "sub_batch": sub, "outputs_checked": "all"}
+
+
+def _party_context(mk, k):
+    P = mk.Params(**PARTY_SETS[k])
+    ctx = mk.Context(P, SEED + k)
+    for i in range(k):
+        ctx.keygen(i, (SEED + 100 * k + i) & 0xFFFFFFFFFFFFFFFF)
+    ctx.upload()
+    return ctx
+
+
+def c3_multiplier(torch, mk, pairs):
+    """Config 3: the 8-bit array multiplier on `pairs` pairs from [-128, 127]
+    with 4 parties (a from party 0, b from party 3), one eager evaluation
+    level by level; every product decrypted."""
+    ctx = _party_context(mk, 4)
+    try:
+        r = operator_rate(torch, mk, ctx, pairs, "mul", bits=8, graph=False, parties=(0, 3), seed=3)
+    finally:
+        ctx.close()
+        torch.cuda.empty_cache()
+    r["parties"] = 4
+    return r
+
+
+def _wrap16(v):
+    v = np.asarray(v, np.int64) & 0xFFFF
+    return np.where(v >= 0x8000, v - 0x10000, v)
+
+
+def _gd_step_plain(X, y, w, shift=12):
+    """One gradient-descent step on Q8.8 integers as the netlist computes it:
+    r_i = sum_j X_ij w_j - y_i and g_j = sum_i X_ij r_i with every product
+    (a b) >> 8 and every sum wrapped to 16 bits, then w_j - (g_j >> shift)
+    (learning rate 2^-6 times 1/m = 2^-6 as one arithmetic shift)."""
+    mul = lambda a, b: _wrap16((np.int64(a) * np.int64(b)) >> 8)
+    m, d = X.shape
+    r = []
+    for i in range(m):
+        acc = mul(X[i, 0], w[0])
+        for j in range(1, d):
+            acc = _wrap16(acc + mul(X[i, j], w[j]))
+        r.append(_wrap16(acc - y[i]))
+    out = []
+    for j in range(d):
+        acc = mul(X[0, j], r[0])
+        for i in range(1, m):
+            acc = _wrap16(acc + mul(X[i, j], r[i]))
+        out.append(_wrap16(w[j] - (int(acc) >> shift)))
+    return np.array(out, np.int64)
+
+
+def c5_lr_step(torch, mk, ctx, m=64, d=4):
+    """Config 5: one encrypted gradient-descent iteration of linear
+    regression on m samples and d features (Q8.8, 16-bit), features split
+    between the two parties (features < d/2, y and w from party 0, the rest
+    from party 1), one eager evaluation level by level; the new weights are
+    decrypted and checked against the plain integer step."""
+    circ = mk.build_lr_step(m, d)
+    levels, live, width, _ = mk.circuit_stats(circ)
+    X, y, w_true = mi.lr_data(m, d, seed=5)
+    w = np.clip(np.rint(w_true * 256 * 0.5), -32768, 32767).astype(np.int64)
+    bits = mi.to_bits(np.concatenate([X.ravel(), y, w]), 16).reshape(-1)
+    owner = np.concatenate([np.repeat([0 if j < (d + 1) // 2 else 1 for j in range(d)] * m, 16),
+                            np.zeros(16 * (m + d), np.int64)])
+    words = ctx.params.lwe_words
+    in_ct = np.zeros((len(bits), 1, words), np.uint32)
+    for p in (0, 1):
+        sel = np.nonzero(owner == p)[0]
+        in_ct[sel, 0] = ctx.encrypt(p, bits[sel], seed=900 + p)
+    dev = torch.device("cuda:0")
+    inp = torch.from_numpy(in_ct.view(np.int32)).to(dev)
+    out = torch.zeros((len(circ.outputs), 1, words), dtype=torch.int32, device=dev)
+    print("bench: LR step (%d levels, %d gates) running" % (levels, live), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.eval_circuit(circ, inp, out)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.device_status()
+    dec = np.stack([ctx.decrypt(o) for o in out.cpu().numpy().view(np.uint32)])[:, 0]
+    got = mi.from_bits(dec.reshape(d, 16))
+    assert np.array_equal(got, _gd_step_plain(X, y, w)), "LR step weights"
+    print("bench: LR step %.1f s, weights correct" % dt, file=sys.stderr, flush=True)
+    return {"m": m, "d": d, "levels": levels, "gates": live, "widest_level": width, "seconds": dt,
+            "gates_per_s": live / dt, "steps_per_s": 1.0 / dt, "outputs_checked": "all"}
 
 
 def formula_lr(torch, mk, ctx, sets, m=64, frac=8):
@@ -352,17 +500,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--path", choices=["mfma", "i32"], default="mfma")
-    ap.add_argument("--cpu-gates-per-core", type=int, default=1)
-    ap.add_argument("--operator-pairs", type=int, default=1024,
-                    help="operand pairs of the 16-bit adder timed through a HIP graph (0: skip)")
-    ap.add_argument("--all-operator-pairs", type=int, default=0,
-                    help="operand pairs of the 16-bit adder, subtractor, multiplier and divider runs "
-                         "(0: skip; minutes at 1024 pairs)")
+    ap.add_argument("--cpu-gates-per-core", type=int, default=8)
+    ap.add_argument("--c3-pairs", type=int, default=256,
+                    help="operand pairs of the 4-party 8-bit multiplier (config 3; 0: skip)")
+    ap.add_argument("--c4", default="add=4096,sub=4096,mul=256,div=256",
+                    help="16-bit operators and their operand pairs (config 4; empty: skip); the adder, "
+                         "subtractor and multiplier run through HIP graphs, the divider eagerly")
+    ap.add_argument("--c5", type=int, default=1, help="run the LR gradient-descent step (config 5; 0: skip)")
     ap.add_argument("--batch-sizes", default="2048,4096",
                     help="larger batches of the same gate mix to time (comma list; 0 or empty: skip)")
     ap.add_argument("--operator-subbatch", type=int, default=0,
-                    help="with --all-operator-pairs: run the multiplier and divider eagerly in sub-batches "
-                         "of this many pairs (0: one batch)")
+                    help="run the 16-bit multiplier and divider eagerly in sub-batches of this many pairs "
+                         "(0: one batch)")
     ap.add_argument("--party-gates", type=int, default=1024,
                     help="gates per batch of the 4- and 8-party runs (0: skip)")
     ap.add_argument("--formula-sets", type=int, default=0,
@@ -454,13 +603,28 @@ def main():
         ms, launches = ctx.get_profile(reset=True)
         return dt / steps, ms, launches
 
-    sec, _, _ = timed(head, args.steps, args.warmup, level=1)
+    sec, hms, hln = timed(head, args.steps, args.warmup, level=1)
     value = BATCH / sec
     # one more step with events around every rotation kernel: per-kernel times
     _, ms, ln = timed(head, 1, 0, level=2)
     br_ms = ms[1] / max(ln[1], 1)
     macs = macs_per_gate(C2) * BATCH
-    if head == mk.PATH_MFMA_I8:
+    persistent = head == mk.PATH_MFMA_I8 and ln[4] > 0 and ln[5] == 0
+    if persistent:
+        # dominant kernel: the persistent rotation (all 1120 CMux steps of
+        # the batch in one launch); executed int8 ops with live-slot skipping
+        ops = executed_int8_ops_per_gate(C2) * BATCH
+        kms = ms[4] / ln[4]
+        achieved = ops / (kms * 1e-3)
+        traffic = measured_traffic("persist", PERSIST_KERNEL)
+        roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_INT8_OPS / 1e12,
+                "unit": "TOP/s", "frac": achieved / PEAK_INT8_OPS, "traffic": traffic,
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "kernel": PERSIST_KERNEL, "avg_launch_ms": kms, "launches": ln[4],
+                "int8_ops_per_launch": ops,
+                "hbm_GBs": traffic / (kms * 1e-3) / 1e9 if traffic else None,
+                "full_hybrid_product_tops": 8 * macs / (kms * 1e-3) / 1e12}
+    elif head == mk.PATH_MFMA_I8:
         # dominant kernel: the stage-1 GEMM.  During party i's steps only the
         # live accumulator slots j <= i+1 are non-zero, so a launch computes
         # 2*live*ell of the products (c'_j and w_j for live j); int8 ops =
@@ -471,20 +635,19 @@ def main():
         g1_ms = ms[4] / max(ln[4], 1)
         achieved = g1_ops / (g1_ms * 1e-3)
         kname = GEMM1_KERNEL[tiles[0]]
+        traffic = measured_traffic("gemm1", kname)
         roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_INT8_OPS / 1e12,
-                "unit": "TOP/s", "frac": achieved / PEAK_INT8_OPS, "traffic": measured_traffic(kname),
-                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
-                                "copy-calibrated)",
-                "kernel": kname, "avg_launch_ms": g1_ms,
-                "hbm_GBs": (measured_traffic(kname) / (g1_ms * 1e-3) / 1e9
-                            if measured_traffic(kname) else None),
-                "launches": ln[4],
+                "unit": "TOP/s", "frac": achieved / PEAK_INT8_OPS, "traffic": traffic,
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "kernel": kname, "avg_launch_ms": g1_ms, "launches": ln[4],
+                "hbm_GBs": traffic / (g1_ms * 1e-3) / 1e9 if traffic else None,
                 "whole_rotation_tops": 8 * macs / (br_ms * 1e-3) / 1e12}
     else:
         achieved = macs / (br_ms * 1e-3)
         roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_TORUS_MACS / 1e12,
                 "unit": "T Torus32-MAC/s", "frac": achieved / PEAK_VALU_TORUS_MACS, "traffic": None,
                 "kernel": "br_plain_kernel", "avg_launch_ms": br_ms}
+    ctx.device_status()
     print("bench: headline measured", file=sys.stderr, flush=True)
     res = {
         "metric": "bootstrapped MK gates/sec on 1 MI355X (int8-MFMA batched vs int32 plain), bit-exact",
@@ -497,20 +660,29 @@ def main():
                    "global_batch": BATCH, "path": args.path, "parallelism": "single GPU"},
         "tiles": {"gemm1_shape": tiles[0], "gemm2_shape": tiles[1], "candidate_ms": tiles[2],
                   "sub_batches": ctx.get_split(BATCH)},
-        "stage_ms_per_step": {"precombine": ms[0], "blind_rotate": ms[1],
-                              "extract_keyswitch": ms[2], "mfma_gemm1": ms[4], "mfma_gemm2": ms[5],
-                              "rotdec": ms[6], "wdec": ms[7]},
+        # stage times of the timed steps (HIP events around each stage, per
+        # step); kernel times from one extra step with events around every
+        # rotation kernel as well
+        "stage_ms_per_step": {"precombine": hms[0] / args.steps, "blind_rotate": hms[1] / args.steps,
+                              "extract_keyswitch": hms[2] / args.steps},
+        "kernel_ms_instrumented_step": ({"persistent_rotation": ms[4], "blind_rotate_stage": ms[1]}
+                                        if persistent else
+                                        {"mfma_gemm1": ms[4], "mfma_gemm2": ms[5], "rotdec": ms[6],
+                                         "wdec": ms[7], "blind_rotate_stage": ms[1]}),
+        "rotation_schedule": "persistent" if persistent else "stream-ordered",
         "roofline": roof,
         "cpu_baseline": cpu,
     }
-    if head == mk.PATH_MFMA_I8 and args.operator_pairs > 0:
-        res["operators"] = operator_rate(torch, mk, ctx, args.operator_pairs)
-        print("bench: operators measured", file=sys.stderr, flush=True)
-    if head == mk.PATH_MFMA_I8 and args.all_operator_pairs > 0:
-        res["operators_16bit"] = {op: operator_rate(torch, mk, ctx, args.all_operator_pairs, op, graph=op != "div",
-                                                    sub=args.operator_subbatch if op in ("mul", "div") else 0)
-                                  for op in OPERATORS}
-        print("bench: 16-bit operators measured", file=sys.stderr, flush=True)
+    if head == mk.PATH_MFMA_I8 and args.c3_pairs > 0:
+        res["c3_multiplier8_4party"] = c3_multiplier(torch, mk, args.c3_pairs)
+    c4 = dict((kv.split("=")[0], int(kv.split("=")[1])) for kv in args.c4.split(",") if "=" in kv)
+    if head == mk.PATH_MFMA_I8 and c4:
+        res["c4_operators_16bit"] = {
+            op: operator_rate(torch, mk, ctx, pairs, op, graph=op != "div",
+                              sub=args.operator_subbatch if op in ("mul", "div") else 0)
+            for op, pairs in c4.items() if pairs > 0}
+    if head == mk.PATH_MFMA_I8 and args.c5:
+        res["c5_lr_step"] = c5_lr_step(torch, mk, ctx)
     sizes = [int(x) for x in args.batch_sizes.split(",") if x.strip() and int(x) > 0]
     if head == mk.PATH_MFMA_I8 and sizes:
         res["batch_scaling"] = batch_scaling(torch, mk, ctx, sizes)

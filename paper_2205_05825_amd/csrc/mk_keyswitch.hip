@@ -183,14 +183,21 @@ __device__ __forceinline__ v4i one_hot(uint32_t r, int t, int lb, int sub, int h
 // sum_t 2^(8t) S_t, and stored: column 0 is added atomically to out[g][0]
 // (one addition per party, exact mod 2^32 in any order), columns 1..n go
 // to out[g][1 + i n + c - 1].
+//
+// Tasks (party, column block, gate tile) are numbered with the gate tile
+// fastest, and each XCD runs one contiguous range of them: workgroup b
+// runs on XCD b mod nx (round-robin dispatch), so task = (b mod nx) per +
+// b / nx.  A column block's key tiles (12 MB at the Table 7 shape) are then
+// fetched by at most two XCDs' L2s, instead of by every XCD.
 template <bool LB2>
 __global__ __launch_bounds__(256, 2) void ks_gemm_kernel(const int8_t *__restrict__ tiles,
                                                          const uint32_t *__restrict__ R, KsShape s,
                                                          size_t count, uint32_t *__restrict__ out,
-                                                         size_t stride) {
+                                                         size_t stride, int nx, int per) {
     __shared__ __align__(16) uint4 red[2 * 4 * 4 * 64];
     const int GT = s.GP / 32, CB = (s.CT + kKsMR - 1) / kKsMR;
-    int task = blockIdx.x;
+    int task = (int)(blockIdx.x % (unsigned)nx) * per + (int)(blockIdx.x / (unsigned)nx);
+    if (task >= s.k * CB * GT) return;
     const int gt = task % GT;
     task /= GT;
     const int cb = task % CB, i = task / CB;
@@ -319,13 +326,14 @@ int launch_ks_mfma(mk_ctx *ctx, const uint32_t *acc, uint32_t *out, size_t count
     hipLaunchKernelGGL(ks_round_kernel, dim3((unsigned)GT, (unsigned)((P.N + 63) / 64), (unsigned)P.k),
                        dim3(256), 0, s, acc, sh, count, R, out, stride);
     MK_HIP(hipGetLastError(), "key-switching round launch");
-    const unsigned blocks = (unsigned)(P.k * CB * GT);
+    const int tasks = P.k * CB * GT, nx = std::max(1, D.num_xcd), per = (tasks + nx - 1) / nx;
+    const unsigned blocks = (unsigned)(nx * per);
     if (P.ks_log_base == 2)
         hipLaunchKernelGGL(ks_gemm_kernel<true>, dim3(blocks), dim3(256), 0, s, D.ks_win, R, sh, count, out,
-                           stride);
+                           stride, nx, per);
     else
         hipLaunchKernelGGL(ks_gemm_kernel<false>, dim3(blocks), dim3(256), 0, s, D.ks_win, R, sh, count, out,
-                           stride);
+                           stride, nx, per);
     MK_HIP(hipGetLastError(), "key-switching GEMM launch");
     return MK_OK;
 }
