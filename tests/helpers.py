@@ -187,7 +187,7 @@ def live_levels(circ):
     return {gi: level[g[3]] for gi, g in enumerate(gates) if g[0] != NOT and g[3] in needed}
 
 
-def sampled_level_parity(name, circ, in_ct, evaluate, seed, max_levels=64):
+def sampled_level_parity(name, circ, in_ct, evaluate, seed, max_levels=64, check_unmodified=True):
     """Per-gate oracle parity inside a full-size circuit run, at every level.
 
     One (gate, instance) item is drawn (seeded) from the live bootstrapped
@@ -203,7 +203,9 @@ def sampled_level_parity(name, circ, in_ct, evaluate, seed, max_levels=64):
     ciphertexts (constants as trivial ciphertexts, inputs as given) and the
     result must equal the GPU's output word for word; with a sample at every
     level this checks each level given the one before.  Returns the
-    original run's outputs and the list of (gate, instance) items."""
+    original run's outputs and the list of (gate, instance) items.  With
+    check_unmodified=False only the extended circuit runs (for sub-circuits
+    that are not a user's circuit) and its first outputs are returned."""
     import paper_2205_05825_amd as mk
     K = oracle_keys(name)
     P = K.params
@@ -227,9 +229,12 @@ def sampled_level_parity(name, circ, in_ct, evaluate, seed, max_levels=64):
     n0 = len(circ.outputs)
     ext = mk.Circuit(circ.n_wires, circ.inputs, np.concatenate([circ.outputs, np.array(extra, np.int32)]),
                      circ.gates)
-    plain = evaluate(circ)
     got = evaluate(ext)
-    assert np.array_equal(plain, got[:n0]), "exposing internal wires changed the outputs"
+    if check_unmodified:
+        plain = evaluate(circ)
+        assert np.array_equal(plain, got[:n0]), "exposing internal wires changed the outputs"
+    else:
+        plain = got[:n0]
     input_pos = {int(w): i for i, w in enumerate(circ.inputs)}
 
     def wire_ct(w, row, inst):
@@ -249,3 +254,52 @@ def sampled_level_parity(name, circ, in_ct, evaluate, seed, max_levels=64):
            if not np.array_equal(j.result(), got[n0 + 3 * k + 2, p[1], :W])]
     assert not bad, bad
     return plain, picks
+
+
+def split_by_levels(circ, parts):
+    """Cuts a netlist into `parts` consecutive sub-netlists by bootstrapping
+    level (as the engine levels it), keeping the wire numbering.  Part k
+    holds the live bootstrapped gates of its level range and the NOT gates
+    at those levels; its inputs are the wires it reads that earlier parts
+    (or the circuit's inputs) define, its outputs the wires it defines that
+    later parts read or the circuit outputs.  Evaluating the parts in order
+    computes exactly the gates of the whole circuit.  Returns a list of
+    paper_2205_05825_amd.Circuit."""
+    import paper_2205_05825_amd as mk
+    NOT = 6
+    gates = [tuple(int(x) for x in g) for g in circ.gates]
+    level = {int(w): 0 for w in list(circ.inputs) + [0, 1]}
+    for t, a, b, o in gates:
+        level[o] = level[a] if t == NOT else 1 + max(level[a], level[b])
+    needed = set(int(w) for w in circ.outputs)
+    for t, a, b, o in reversed(gates):
+        if o in needed:
+            needed.update([a] if t == NOT else [a, b])
+    L = max([level[o] for t, a, b, o in gates if o in needed] + [1])
+    part_of = lambda lv: 0 if lv <= 0 else min(parts - 1, (lv - 1) * parts // L)
+    owner = {}
+    members = [[] for _ in range(parts)]
+    for t, a, b, o in gates:
+        if o not in needed:
+            continue
+        k = part_of(level[o])
+        owner[o] = k
+        members[k].append((t, a, b, o))
+    later_reads = [set() for _ in range(parts)]
+    for k in range(parts):
+        for t, a, b, o in members[k]:
+            for w in ([a] if t == NOT else [a, b]):
+                if w in owner and owner[w] < k:
+                    later_reads[owner[w]].add(w)
+    out = []
+    for k in range(parts):
+        defined = {o for _, _, _, o in members[k]}
+        ins = []
+        for t, a, b, o in members[k]:
+            for w in ([a] if t == NOT else [a, b]):
+                if w not in defined and w not in (0, 1) and w not in ins:
+                    ins.append(w)
+        outs = sorted(w for w in defined if w in later_reads[k] or w in set(int(x) for x in circ.outputs))
+        g = np.array([list(x) for x in members[k]], np.int32).reshape(-1, 4)
+        out.append(mk.Circuit(circ.n_wires, np.array(ins, np.int32), np.array(outs, np.int32), g))
+    return out

@@ -196,3 +196,23 @@ def test_c5_lr_step_full(torch_cuda):
           % (levels, live, width, timing["dt"], live / timing["dt"]))
     assert np.array_equal(mi.from_bits(dec.reshape(d, 16)), lr.replica_step(X, y, w))
 
+
+
+def test_add16_2200_pairs_chunked_levels(torch_cuda):
+    """The 16-bit adder on 2200 pairs at the Table 7 shape: its widest level
+    (31 gates x 2200 pairs = 68 200 gates) is more than one rotation launch
+    takes (65 536), so it runs in two chunks that read and write the wire
+    buffer while the level is in flight (the case a slot-reuse bug once
+    broke).  Every sum decrypts to a + b, the unmodified circuit's outputs
+    equal the extended run's, and one gate per level matches the oracle."""
+    import paper_2205_05825_amd as mk
+    K, ctx = helpers.gpu_world("C2")
+    circ = mk.build_operator(mk.OP_ADD, 16)
+    assert mk.circuit_stats(circ)[2] * 2200 > 65536
+    a, b = mi.operand_pairs(2200, 16, seed=22)
+    in_ct = np.concatenate([_enc_operand(ctx, a, 16, 0, 2201), _enc_operand(ctx, b, 16, 1, 2202)])
+    outs, picks = helpers.sampled_level_parity("C2", circ, in_ct, lambda c: _words(torch_cuda, ctx, c, in_ct)[0],
+                                               seed=2203)
+    assert len(picks) == mk.circuit_stats(circ)[0]
+    dec = np.stack([ctx.decrypt(x) for x in outs])
+    assert np.array_equal(mi.from_bits(dec.T), _wrap(a + b, 16))
