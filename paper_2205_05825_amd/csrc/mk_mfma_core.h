@@ -310,8 +310,9 @@ __host__ __device__ constexpr int pow2_at_least(int v) {
     while (m < v) m *= 2;
     return m;
 }
-template <int MR, int NB, int D, int DAUX, int NC = 1, class Init>
-__device__ __forceinline__ void slide_gemm(const Operands &o, int t, int lane, v16i (&acc)[MR][NC], Init init) {
+template <int MR, int NB, int D, int DAUX, int NC, bool SEG, int PF, class Init, class Pre, class Put, class Settle>
+__device__ __forceinline__ void slide_core(const Operands &o, int seg, int t, int lane, v16i (&acc)[MR][NC], Init init,
+                                           Pre pre, Put put, Settle settle) {
     constexpr int ND = 2 * NB - 1;
     constexpr int RK = pow2_at_least(D + 1), RB = pow2_at_least(MR + D);
     constexpr int RN = MR > 1 ? MR - 1 : 1;
@@ -319,8 +320,8 @@ __device__ __forceinline__ void slide_gemm(const Operands &o, int t, int lane, v
     static_assert(NB % RK == 0 && NB % RB == 0 && D + MR - 1 < NB && D < X0, "ring sizes for this N");
     const int ell = o.ell;
     const int nv = o.nc_valid > 0 ? o.nc_valid : 0;
-    const __amdgpu_buffer_rsrc_t ra =
-        __builtin_amdgcn_make_buffer_rsrc((void *)o.A, (short)0, ell * 4 * ND * kTileBytes, kBufWord3);
+    const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)o.A, (short)0, (SEG ? seg : ell) * 4 * ND * kTileBytes, kBufWord3);
     const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(
         (void *)o.B, (short)0, (int)((ell - 1) * o.b_poly + nv * NB * kTileBytes), kBufWord3);
     const uint32_t lane16 = (uint32_t)lane * 16;
@@ -331,12 +332,14 @@ __device__ __forceinline__ void slide_gemm(const Operands &o, int t, int lane, v
 #pragma unroll
     for (int c = 0; c < NC; ++c) vd[c] = c < o.nc_valid ? (uint32_t)c * NB * kTileBytes + lane16 : kOutOfRange;
     // byte offsets of polynomial p's main-row key at x = 0, its next-row key
-    // at x = 0 (the term - x KB is added per step), and its digit block
+    // at x = 0 (the term - x KB is added per step), and its digit block;
+    // with segments, polynomial p multiplies key p mod seg
+    auto kpos = [&](int p) -> uint32_t { return (uint32_t)(SEG ? p % seg : p) * kpoly; };
     auto kmain = [&](int p) -> uint32_t {
-        return (p >= 0 && p < ell) ? p * kpoly + klimb + (uint32_t)(o.mb0 + NB - 1) * kTileBytes : kOutOfRange;
+        return (p >= 0 && p < ell) ? kpos(p) + klimb + (uint32_t)(o.mb0 + NB - 1) * kTileBytes : kOutOfRange;
     };
     auto knext = [&](int p) -> uint32_t {   // p = polynomial of the next rows
-        return (p >= 0 && p < ell) ? p * kpoly + klimb + (uint32_t)(o.mb0 + 2 * NB - 1) * kTileBytes
+        return (p >= 0 && p < ell) ? kpos(p) + klimb + (uint32_t)(o.mb0 + 2 * NB - 1) * kTileBytes
                                    : kOutOfRange;
     };
     // digit block of polynomial p, gate tile g (zeros outside the operand)
@@ -375,13 +378,17 @@ __device__ __forceinline__ void slide_gemm(const Operands &o, int t, int lane, v
     };
     // multiplications of step x: rows on polynomial i (main, skipped in the
     // leading iteration) and rows already on polynomial i + 1 (in the last
-    // iteration their key tiles read as zero)
+    // iteration their key tiles read as zero).  The row whose K range ends
+    // at this step (x = NB - 1 - r) goes first, so that its result is ready
+    // while the step's other products run.
     auto mult = [&](auto xc, auto lead) {
         constexpr int x = decltype(xc)::value;
+        constexpr int r0 = (NB - 1 - x >= 0 && NB - 1 - x < MR) ? NB - 1 - x : 0;
 #pragma unroll
-        for (int r = 0; r < MR; ++r)
+        for (int k = 0; k < MR; ++k)
 #pragma unroll
             for (int g = 0; g < NC; ++g) {
+                const int r = (k + r0) % MR;
                 if (x + r < NB) {
                     if constexpr (!decltype(lead)::value)
                         acc[r][g] = __builtin_amdgcn_mfma_i32_32x32x32_i8(km[x % RK], dg[(x + r) % RB][g], acc[r][g],
@@ -405,14 +412,64 @@ __device__ __forceinline__ void slide_gemm(const Operands &o, int t, int lane, v
         }
         __builtin_amdgcn_sched_barrier(0);
     });
+    [[maybe_unused]] v4i old[MR];
+    int s = 0, left = seg;   // segments: segment of iteration i, iterations left in it
     for (int i = 0; i < ell; ++i) {
         set_iter(i);
+        // segment boundary: rows finish segment s in this iteration
+        [[maybe_unused]] bool last = false;
+        if constexpr (SEG) last = --left == 0;
         static_for<0, NB>([&](auto xc) {
+            constexpr int x = decltype(xc)::value;
             issue(xc);
+            if constexpr (SEG) {
+                // row rp finishes PF steps from now: fetch what settle needs
+                constexpr int rp = NB - 1 - (x + PF);
+                if constexpr (rp >= 0 && rp < MR)
+                    if (last) old[rp] = pre(rp, s);
+            }
             mult(xc, std::false_type{});
+            if constexpr (SEG) {
+                // row rf multiplied the last K-block of the segment at this step
+                constexpr int rf = NB - 1 - x;
+                if constexpr (rf >= 0 && rf < MR)
+                    if (last) {
+                        put(rf);
+                        acc[rf][0] = v16i{};
+                    }
+            }
             __builtin_amdgcn_sched_barrier(0);
         });
+        if constexpr (SEG)
+            if (last) {
+                settle(s, old);
+                ++s;
+                left = seg;
+            }
     }
+}
+
+template <int MR, int NB, int D, int DAUX, int NC = 1, class Init>
+__device__ __forceinline__ void slide_gemm(const Operands &o, int t, int lane, v16i (&acc)[MR][NC], Init init) {
+    slide_core<MR, NB, D, DAUX, NC, false, 0>(o, 0, t, lane, acc, init, [](int, int) { return v4i{}; },
+                                              [](int) {}, [](int, const v4i (&)[MR]) {});
+}
+
+// The seamless contraction over o.ell = S seg polynomials cut into S
+// segments of seg: polynomial p multiplies key polynomial p mod seg (the
+// same key for every segment) and digit block p.  Row tile r finishes
+// segment s at step NB - 1 - r of the segment's last iteration: right after
+// that multiplication put(r) takes the row's limb accumulators (acc[r]),
+// which restart from zero for segment s + 1 with the row's next product
+// (one step later).  After the iteration, settle(s, old) completes the
+// segment's rows; old[r] is what pre(r, s) returned, PF steps before row
+// r's put (a load in flight meanwhile).  Rows finish one per step, from
+// r = MR - 1 to 0.
+template <int MR, int NB, int D, int DAUX, int PF, class Pre, class Put, class Settle>
+__device__ __forceinline__ void slide_gemm_seg(const Operands &o, int seg, int t, int lane, v16i (&acc)[MR][1],
+                                               Pre pre, Put put, Settle settle) {
+    static_assert(NB - MR - PF >= 0, "the first prefetch must fall inside the segment's last iteration");
+    slide_core<MR, NB, D, DAUX, 1, true, PF>(o, seg, t, lane, acc, []() {}, pre, put, settle);
 }
 
 // Limb-split contraction whose digit tiles reach the four waves through

@@ -14,9 +14,11 @@
 //           w = sum_{j<L} sum_l T(b_{j,l}) U_{j,l}
 //       over all L*ell key polynomials in one accumulation, and decompose w
 //       into the digit planes V; members RB..2RB-1 (rb = member - RB) add
-//       c'_j = sum_l T(d_l) U_{j,l} into ACC_j for every j < L.  Both
-//       halves contract L*ell polynomials, so the phase is balanced for
-//       every L.
+//       c'_j = sum_l T(d_l) U_{j,l} into ACC_j for every j < L, as one
+//       seamless stream of L*ell polynomials cut into L segments (a row
+//       tile hands its finished c'_j to LDS and restarts for c'_{j+1}
+//       without draining the pipeline).  Both halves contract L*ell
+//       polynomials.
 //   S2  ACC_{o ? 1+i : 0} += sum_l T(f_o,l) V_l, one (o, rb) task per member.
 // This is the hybrid product of the uni-encrypted bootstrapping key (§3.2)
 // with the evaluation key (b_0 = -a, b_1..b_k), in the same order as the
@@ -71,11 +73,11 @@ constexpr int kLimbTileBytes = 4 * 4 * 64 * 16;     // one row tile's four limbs
 // NB, see slide_gemm).
 template <int NB>
 struct PersistCfg;
-template <> struct PersistCfg<4> { static constexpr int MR = 2, D = 2, OCC = 2; };
-template <> struct PersistCfg<8> { static constexpr int MR = 4, D = 4, OCC = 2; };
-template <> struct PersistCfg<16> { static constexpr int MR = 4, D = 4, OCC = 2; };
-template <> struct PersistCfg<32> { static constexpr int MR = 8, D = 6, OCC = 1; };
-template <> struct PersistCfg<64> { static constexpr int MR = 8, D = 6, OCC = 1; };
+template <> struct PersistCfg<4> { static constexpr int MR = 2, D = 2, OCC = 2, PF = 2; };
+template <> struct PersistCfg<8> { static constexpr int MR = 4, D = 4, OCC = 2, PF = 4; };
+template <> struct PersistCfg<16> { static constexpr int MR = 4, D = 4, OCC = 2, PF = 4; };
+template <> struct PersistCfg<32> { static constexpr int MR = 8, D = 6, OCC = 1, PF = 10; };
+template <> struct PersistCfg<64> { static constexpr int MR = 8, D = 6, OCC = 1, PF = 4; };
 
 struct PersistArgs {
     MfmaArgs m;
@@ -288,7 +290,9 @@ __device__ __forceinline__ void store_v_digits(const MfmaArgs &a, int tile, int 
 }
 
 // One contraction task on tile t, row block rb, wave w = key limb: kind 0 =
-// c'_j into ACC_j, 1 = w into V, 2 = stage-2 unit o into ACC_{o ? 1+party : 0}.
+// c'_j into ACC_j for every live slot j (one seamless stream of live x ell
+// polynomials, one segment per slot), 1 = w into V, 2 = stage-2 unit o into
+// ACC_{o ? 1+party : 0}.
 template <int NB>
 __device__ __forceinline__ void task_gemm(const PersistArgs &p, int kind, int j_or_o, int t, int rb, int party,
                                           int bit, int live, uint4 *red) {
@@ -299,15 +303,68 @@ __device__ __forceinline__ void task_gemm(const PersistArgs &p, int kind, int j_
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
     const size_t poly_tiles = (size_t)4 * ND * kTileBytes;
     const size_t bkbit = ((size_t)party * a.n + bit) * 3;
-    Operands o;
-    uint32_t *base = a.acc;
     const size_t gate_stride = (size_t)K1 * N;
+    Operands o;
+    o.b_poly = (uint32_t)((size_t)GT * NB * kTileBytes);
+    o.NB = NB;
+    o.mb0 = rb * MR;
+    o.nc_valid = 1;
+    v16i acc[MR][1];
+#pragma unroll
+    for (int r = 0; r < MR; ++r) acc[r][0] = v16i{};
     if (kind == 0) {
+        // d_l against U_{j,l} for j < live: polynomial p = j ell + l
         o.A = a.bk + bkbit * ell * poly_tiles;
-        o.B = a.U + ((size_t)j_or_o * ell * GT + t) * NB * kTileBytes;
-        o.ell = ell;
-        base = a.acc + (size_t)j_or_o * N;
-    } else if (kind == 1) {
+        o.B = a.U + (size_t)t * NB * kTileBytes;
+        o.ell = live * ell;
+        // the tile's gates: lane g's row tile r of slot s starts at word
+        // g K1 N + s N + 32 (rb MR + r); wave w owns words 8 w + 4 h .. + 3
+        const __amdgpu_buffer_rsrc_t racc = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(a.acc + (size_t)t * 32 * gate_stride), (short)0, (int)(32 * gate_stride * 4), kBufWord3);
+        const uint32_t lane_word =
+            (uint32_t)((size_t)(lane & 31) * gate_stride + 32 * rb * MR + 8 * w + 4 * (lane >> 5));
+        uint32_t *tile_acc = a.acc + (size_t)t * 32 * gate_stride;
+        // a segment's rows go to LDS one by one as they finish (row r in
+        // slot r, [wave][quad][lane]); after the segment's last iteration,
+        // one barrier, then wave w sums quad w of the four limbs of every
+        // row, limb l weighted 2^(8 l), onto the row's old value.  A second
+        // barrier before the first put keeps a segment's puts clear of the
+        // previous segment's reads.
+        uint4 *slots = red;
+        slide_gemm_seg<MR, NB, PersistCfg<NB>::D, kCoherent, PersistCfg<NB>::PF>(
+            o, ell, w, lane, acc,
+            [&](int r, int s) { return ld_coherent(racc, (lane_word + (uint32_t)(s * N + 32 * r)) * 4u); },
+            [&](int r) {
+                if (r == MR - 1) __syncthreads();
+                uint4 *slot = slots + r * (4 * 4 * 64);
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    slot[(w * 4 + q) * 64 + lane] =
+                        make_uint4((uint32_t)acc[r][0][4 * q + 0], (uint32_t)acc[r][0][4 * q + 1],
+                                   (uint32_t)acc[r][0][4 * q + 2], (uint32_t)acc[r][0][4 * q + 3]);
+            },
+            [&](int s, const v4i (&old)[MR]) {
+                __syncthreads();
+#pragma unroll
+                for (int r = 0; r < MR; ++r) {
+                    const uint4 *slot = slots + r * (4 * 4 * 64);
+                    uint4 v = make_uint4((uint32_t)old[r][0], (uint32_t)old[r][1], (uint32_t)old[r][2],
+                                         (uint32_t)old[r][3]);
+#pragma unroll
+                    for (int l = 0; l < 4; ++l) {
+                        const uint4 x = slot[(l * 4 + w) * 64 + lane];
+                        v.x += x.x << (8 * l);
+                        v.y += x.y << (8 * l);
+                        v.z += x.z << (8 * l);
+                        v.w += x.w << (8 * l);
+                    }
+                    *reinterpret_cast<uint4 *>(tile_acc + lane_word + (size_t)s * N + 32 * r) = v;
+                }
+            });
+        return;
+    }
+    uint32_t *base = a.acc;
+    if (kind == 1) {
         o.A = a.evk;                                   // b_{j,l}, j < live, flattened
         o.B = a.U + (size_t)t * NB * kTileBytes;       // U_{j,l}, same order
         o.ell = live * ell;
@@ -317,13 +374,6 @@ __device__ __forceinline__ void task_gemm(const PersistArgs &p, int kind, int j_
         o.ell = ell;
         base = a.acc + (size_t)(j_or_o == 0 ? 0 : 1 + party) * N;
     }
-    o.b_poly = (uint32_t)((size_t)GT * NB * kTileBytes);
-    o.NB = NB;
-    o.mb0 = rb * MR;
-    o.nc_valid = 1;
-    v16i acc[MR][1];
-#pragma unroll
-    for (int r = 0; r < MR; ++r) acc[r][0] = v16i{};
     // the tile's rows of the read-modify-write output (w has none)
     const __amdgpu_buffer_rsrc_t rbase = __builtin_amdgcn_make_buffer_rsrc(
         (void *)(base + (size_t)t * 32 * gate_stride), (short)0, (int)(32 * gate_stride * 4), kBufWord3);
@@ -386,12 +436,10 @@ __global__ __launch_bounds__(kPThreads, PersistCfg<NB>::OCC) void persist_rotati
         // S1 (phase 1) and S2 (phase 2); one call site for every contraction
         // task keeps a single copy of it
         for (int ph = 1; ph <= 2; ++ph) {
-            // tasks of this member per tile: S1 w (1) or c'_0..c'_{L-1}; S2 one
-            const int per = ph == 2 ? 1 : (r < RB ? 1 : L);
-            for (int it = 0; it < c * per; ++it) {
-                const int ti = it / per, k = it % per;
+            // one task of this member per tile: S1 w or c'_0..c'_{L-1}, S2 (o, rb)
+            for (int ti = 0; ti < c; ++ti) {
                 const int kind = ph == 2 ? 2 : (r < RB ? 1 : 0);
-                const int jo = ph == 2 ? r / RB : k;
+                const int jo = ph == 2 ? r / RB : 0;
                 const int rb = ph == 2 ? r % RB : (r < RB ? r : r - RB);
                 task_gemm<NB>(p, kind, jo, x + (tile0 + ti) * p.nx, rb, party, bit, L, red);
             }

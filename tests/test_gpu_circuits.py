@@ -252,3 +252,41 @@ def test_naive_gates_parity(torch_cuda, t):
     assert np.array_equal(got, helpers.oracle_circuit("C1B", C.naive_gate(t), in_ct))
     want = [1 - x for x in a] if t == mk.NOT else [mi.plain_gate(t, int(x), int(y)) for x, y in zip(a, b)]
     assert tfhe.decrypt(K, got[0]).tolist() == want
+
+
+@pytest.mark.parametrize("piece", [64, 4096])
+def test_graph_piece_sizes(torch_cuda, piece):
+    """Graphs cut into pieces of 64 and of 4096 kernels (the bounds
+    mk_set_graph_piece accepts): two replays equal the eager evaluation word
+    for word, and the piece count follows the size."""
+    import paper_2205_05825_amd as mk
+    K, ctx = helpers.gpu_world("C1B")
+    k, batch = 4, 7
+    circ = mk.build_operator(0, k)
+    W = K.params.lwe_words
+    d = torch_cuda.device("cuda:0")
+    a = np.arange(batch) - 3
+    b = 5 - 2 * np.arange(batch)
+    in_ct = np.concatenate([helpers.encrypt_operands(K, a, k, 0, 7200 + piece),
+                            helpers.encrypt_operands(K, b, k, 1, 7300 + piece)])
+    inp = torch_cuda.from_numpy(np.ascontiguousarray(in_ct).view(np.int32)).to(d)
+    out = torch_cuda.full((len(circ.outputs), batch, W), -1, dtype=torch_cuda.int32, device=d)
+    eager = _eval(torch_cuda, ctx, circ, in_ct, 1)
+    ctx.set_graph_piece(piece)
+    try:
+        g = ctx.circuit_graph(circ, inp, out, path=1)
+    finally:
+        ctx.set_graph_piece(1024)
+    try:
+        pieces = g.info()[2]
+        levels = mk.circuit_stats(circ)[0]
+        # 4 kernels per stream-ordered CMux step (k n = 128 steps per level)
+        assert pieces >= levels * 4 * 128 // piece
+        for _ in range(2):
+            g.launch()
+            torch_cuda.cuda.synchronize()
+            assert np.array_equal(out.cpu().numpy().view(np.uint32), eager)
+    finally:
+        g.close()
+    dec = np.stack([tfhe.decrypt(K, o) for o in eager])
+    assert np.array_equal(mi.from_bits(dec.T), _wrap(a + b, k))
