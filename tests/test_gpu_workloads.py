@@ -165,6 +165,7 @@ def test_c4_operators_subset(torch_cuda, op):
         assert np.array_equal(mi.from_bits(dec[16:].T), _wrap(a - q * b, 16))
 
 
+@pytest.mark.timeout(600)
 def test_c5_lr_step_full(torch_cuda):
     """Config 5: one encrypted gradient-descent step on m=64 samples, d=4
     features split between the two parties, 16-bit Q8.8 values, learning rate
