@@ -405,8 +405,8 @@ int mk_get_tiles(const mk_ctx *ctx, size_t count, int32_t *gemm1_shape,
  *                      workgroups runs it, meeting at a barrier after each
  *                      phase of a CMux step (rotate + decompose, stage 1,
  *                      stage 2).  Needs N in {128, 256, 512, 1024, 2048}.
- *   MK_ROT_AUTO        the persistent schedule for batches of at least four
- *                      tiles per XCD (1024 gates on MI355X), where it is
+ *   MK_ROT_AUTO        the persistent schedule for batches of at least 2.5
+ *                      tiles per XCD (640 gates on MI355X), where it is
  *                      faster; stream-ordered kernels below (default).
  * Errors: MK_EINVAL. */
 #define MK_ROT_AUTO -1

@@ -595,14 +595,15 @@ static uint32_t *ctl_of(const MfmaArgs &a) {
 }
 
 // Whether the persistent rotation runs a batch of GT gate tiles: by choice
-// (mk_set_rotation), else from four tiles per XCD on.  Measured on MI355X
-// at the Table 7 shape: 1024 gates (4 tiles per XCD) take 90 ms persistent
-// against 101 ms stream-ordered, while 256 gates take 72 against 50 ms (a
-// team then has too little work per barrier).
+// (mk_set_rotation), else from 2.5 tiles per XCD on.  Measured on MI355X at
+// the Table 7 shape (persistent against stream-ordered): 256 gates 71 / 50
+// ms, 512 gates 73 / 72, 640 gates 75 / 81, 768 gates 78 / 91, 1024 gates
+// 88 / 100 (with fewer tiles a team of 8 CUs per tile leaves most of the
+// chip idle, while the stream-ordered kernels split a tile over many CUs).
 static bool use_persist(const mk_ctx *ctx, int GT) {
     const DeviceKeys &D = ctx->dev;
     if (D.rot_kind == MK_ROT_STREAM || D.num_xcd <= 0 || !persist_supported(ctx->p)) return false;
-    return D.rot_kind == MK_ROT_PERSISTENT || GT >= 4 * D.num_xcd;
+    return D.rot_kind == MK_ROT_PERSISTENT || 2 * GT >= 5 * D.num_xcd;
 }
 
 // Sub-batches of a rotation: a batch can be split in two halves that run on
