@@ -52,7 +52,8 @@ TRAFFIC = {
     "gemm1": (os.path.join(ROOT, "profiles", "mfma_gemm1_c2_1024gates_hbm_traffic.md"),
               [os.path.join(CSRC, "mk_mfma.hip")]),
     "persist": (os.path.join(ROOT, "profiles", "persist_rotation_c2_1024gates_hbm_traffic.md"),
-                [os.path.join(CSRC, "mk_persist.hip"), os.path.join(CSRC, "mk_mfma_core.h")]),
+                [os.path.join(CSRC, "mk_persist.hip"), os.path.join(CSRC, "mk_mfma_core.h"),
+                 os.path.join(CSRC, "mk_ks_core.h")]),
 }
 PERSIST_KERNEL = "persist_rotation_kernel<32>"
 
@@ -610,9 +611,15 @@ def main():
     br_ms = ms[1] / max(ln[1], 1)
     macs = macs_per_gate(C2) * BATCH
     persistent = head == mk.PATH_MFMA_I8 and ln[4] > 0 and ln[5] == 0
+    # extraction and key switching inside the persistent launch: no
+    # separate key-switching stage was timed
+    ks_fused = persistent and ln[2] == 0
     if persistent:
         # dominant kernel: the persistent rotation (all 1120 CMux steps of
-        # the batch in one launch); executed int8 ops with live-slot skipping
+        # the batch in one launch); executed int8 ops with live-slot
+        # skipping.  With key switching fused the launch also switches the
+        # batch (0.3-0.4% of its time); those ops are not counted, so the
+        # achieved rate is slightly conservative.
         ops = executed_int8_ops_per_gate(C2) * BATCH
         kms = ms[4] / ln[4]
         achieved = ops / (kms * 1e-3)
@@ -622,6 +629,8 @@ def main():
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "kernel": PERSIST_KERNEL, "avg_launch_ms": kms, "launches": ln[4],
                 "int8_ops_per_launch": ops,
+                "launch_includes": ("rotation, extraction and key switching (ops: rotation only)"
+                                    if ks_fused else "rotation"),
                 "hbm_GBs": traffic / (kms * 1e-3) / 1e9 if traffic else None,
                 "full_hybrid_product_tops": 8 * macs / (kms * 1e-3) / 1e12}
     elif head == mk.PATH_MFMA_I8:
@@ -670,6 +679,7 @@ def main():
                                         {"mfma_gemm1": ms[4], "mfma_gemm2": ms[5], "rotdec": ms[6],
                                          "wdec": ms[7], "blind_rotate_stage": ms[1]}),
         "rotation_schedule": "persistent" if persistent else "stream-ordered",
+        "key_switch_fused": ks_fused,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

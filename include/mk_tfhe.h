@@ -414,6 +414,14 @@ int mk_get_tiles(const mk_ctx *ctx, size_t count, int32_t *gemm1_shape,
 #define MK_ROT_PERSISTENT 1
 int mk_set_rotation(mk_ctx *ctx, int kind);
 
+/* Where the int8-MFMA path runs sample extraction and key switching (§3.2
+ * MKKeySwitch) after a persistent rotation: on = 1 (default) inside the
+ * rotation's own launch, each team of workgroups switching its own 32-gate
+ * tiles right after their last CMux step; on = 0 as two separate kernels
+ * after the launch (the only form after stream-ordered rotations).  Results
+ * are identical either way.  Errors: MK_EINVAL. */
+int mk_set_ks_fusion(mk_ctx *ctx, int on);
+
 /* Waits for `stream`, then reports and clears the context's device status
  * word, which device entry points set when they meet a condition they can
  * only detect on the GPU: MK_OK; MK_EINVAL if mk_bootstrap_gate met a gate

@@ -75,6 +75,12 @@ TOYB3 = Params(k=3, n=16, N=64, bk_ell=3, ks_t=5,
                bk_noise_log2=30, ks_noise_log2=24, lwe_noise_log2=20, ks_log_base=3)
 
 
+# Smallest MFMA ring with 3 parties and base-8 key switching (3-bit
+# digits): the general one-hot code of the int8-MFMA key switch.
+C1SB3 = Params(k=3, n=32, N=128, bk_ell=2, ks_t=5,
+               bk_noise_log2=26, ks_noise_log2=20, lwe_noise_log2=12, ks_log_base=3)
+
+
 def toy(k: int) -> Params:
     return Params(k=k, n=16, N=64, bk_ell=3, ks_t=8,
                   bk_noise_log2=30, ks_noise_log2=24, lwe_noise_log2=20)

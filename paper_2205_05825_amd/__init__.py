@@ -7,4 +7,5 @@ gfx950.  Import fails if the HIP library has not been built (no fallback).
 """
 from ._lib import (AND, NAND, NOR, NOT, OR, PATH_I32, PATH_MFMA_I8, XNOR, XOR,  # noqa: F401
                    Circuit, Context, Graph, MkError, Params, build_operator, build_lr_step,
-                   build_lr_formula, build_naive_gate, circuit_stats, circuit_slots, EXPORTED, LIB_PATH, OP_ADD, OP_SUB, OP_MUL, OP_DIV, OP_DIV2)
+                   build_lr_formula, build_naive_gate, circuit_stats, circuit_slots, EXPORTED, LIB_PATH, OP_ADD, OP_SUB, OP_MUL, OP_DIV, OP_DIV2,
+                   ROT_AUTO, ROT_STREAM, ROT_PERSISTENT)

@@ -102,6 +102,7 @@ _SIGS = {
     "mk_set_tiles": ([_vp, _i, _i], _i),
     "mk_get_tiles": ([_vp, _sz, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], _i),
     "mk_set_rotation": ([_vp, _i], _i),
+    "mk_set_ks_fusion": ([_vp, _i], _i),
     "mk_device_status": ([_vp, _vp], _i),
     "mk_set_profiling": ([_vp, _i], _i),
     "mk_get_profile": ([_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), _i], _i),
@@ -296,6 +297,11 @@ class Context:
         """Schedule of the MFMA rotation: ROT_STREAM (four kernels per CMux
         step), ROT_PERSISTENT (one launch per rotation) or ROT_AUTO."""
         _check(_L.mk_set_rotation(self._h, int(kind)))
+
+    def set_ks_fusion(self, on: bool = True):
+        """Extraction and key switching inside the persistent rotation's
+        launch (True, default) or as separate kernels after it (False)."""
+        _check(_L.mk_set_ks_fusion(self._h, int(bool(on))))
 
     def device_status(self, stream=None):
         """Waits for the stream; raises MkError if a persistent rotation gave

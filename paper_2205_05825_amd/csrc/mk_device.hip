@@ -503,6 +503,19 @@ int run_key_switch(mk_ctx *ctx, const uint32_t *acc, uint32_t *out, size_t count
     return fail(MK_EINVAL, "unknown path");
 }
 
+int run_rotate_ks(mk_ctx *ctx, const uint32_t *abar, uint32_t *acc, uint32_t *out, size_t count, size_t stride,
+                  int path, hipStream_t s) {
+    int rc;
+    if (path == MK_PATH_MFMA_I8) {
+        bool done = false;
+        if ((rc = launch_br_mfma(ctx, abar, acc, count, ctx->p.k * ctx->p.n, s, out, stride, &done)) || done)
+            return rc;
+    } else if ((rc = run_blind_rotate(ctx, abar, acc, count, ctx->p.k * ctx->p.n, path, s))) {
+        return rc;
+    }
+    return run_key_switch(ctx, acc, out, count, stride, path, s);
+}
+
 // Gates per rotation launch: larger batches (and wide circuit levels) run in
 // chunks, which bounds the scratch memory and keeps the MFMA path's 32-bit
 // digit offsets, K1 ell GP N < 2^31, in range.
@@ -532,9 +545,7 @@ int run_gates(mk_ctx *ctx, const uint8_t *types, const uint32_t *in1, const uint
                                total, abar, ctx->dev.status);
         }
         MK_HIP(hipGetLastError(), "precombine launch");
-        if ((rc = run_blind_rotate(ctx, abar, acc, cnt, P.k * P.n, path, s)) ||
-            (rc = run_key_switch(ctx, acc, out + c0 * stride, cnt, stride, path, s)))
-            return rc;
+        if ((rc = run_rotate_ks(ctx, abar, acc, out + c0 * stride, cnt, stride, path, s))) return rc;
     }
     return MK_OK;
 }

@@ -41,26 +41,38 @@ size_t rotation_chunk(const mk_params &P);
 
 // Int8-MFMA path (mk_mfma.hip).
 int mfma_upload(mk_ctx *ctx, const std::vector<uint32_t> &evk, hipStream_t s);
+// With `ks_out` given and a full rotation (steps = k n) on the persistent
+// schedule with key-switch fusion on, extraction and key switching into
+// ks_out run inside the rotation's launch and *ks_done is set (acc is then
+// left untouched); otherwise the caller runs them.
 int launch_br_mfma(mk_ctx *ctx, const uint32_t *abar, uint32_t *acc, size_t count, int steps,
-                   hipStream_t s);
+                   hipStream_t s, uint32_t *ks_out = nullptr, size_t ks_stride = 0, bool *ks_done = nullptr);
 size_t mfma_scratch_need(const mk_params &P, size_t count);
 // Persistent rotation (mk_persist.hip).
 struct MfmaArgs;
+struct KsFused;
 int persist_probe(mk_ctx *ctx, hipStream_t s);
 size_t persist_ctl_words(int GT);
 bool persist_supported(const mk_params &P);
-int launch_persist(mk_ctx *ctx, const MfmaArgs &m, int steps, uint32_t *ctl, hipStream_t s);
+int launch_persist(mk_ctx *ctx, const MfmaArgs &m, int steps, uint32_t *ctl, const KsFused *ks, hipStream_t s);
 // Key switching as an int8-MFMA GEMM (mk_keyswitch.hip).
 size_t ks_scratch_need(const mk_params &P, size_t count);
 int ks_mfma_upload(mk_ctx *ctx, hipStream_t s);
 int launch_ks_mfma(mk_ctx *ctx, const uint32_t *acc, uint32_t *out, size_t count, size_t stride,
                    hipStream_t s);
+// Arguments of the key switching fused into a persistent rotation of
+// `count` gates (grows the rounded-coefficient scratch).
+int ks_fused_args(mk_ctx *ctx, size_t count, uint32_t *out, size_t stride, hipStream_t s, KsFused *f);
 // During a graph capture: ends the current graph after enough kernels and
 // begins the next one on the same stream (mk_engine.hip).
 int capture_checkpoint(mk_ctx *ctx, hipStream_t s, int kernels);
 // The whole gate pipeline on `count` gates (mk_device.hip).
 int run_gates(mk_ctx *ctx, const uint8_t *types, const uint32_t *in1, const uint32_t *in2,
               uint32_t *out, size_t count, size_t stride, int path, hipStream_t s);
+// Blind rotation of `count` gates, then sample extraction and key switching
+// into `out` (fused into the rotation's launch where that applies).
+int run_rotate_ks(mk_ctx *ctx, const uint32_t *abar, uint32_t *acc, uint32_t *out, size_t count, size_t stride,
+                  int path, hipStream_t s);
 // Sample extraction + key switching on the given path (mk_device.hip).
 int run_key_switch(mk_ctx *ctx, const uint32_t *acc, uint32_t *out, size_t count, size_t stride, int path,
                    hipStream_t s);

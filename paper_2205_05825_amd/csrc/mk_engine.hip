@@ -40,9 +40,6 @@ struct mk_graph {
 
 namespace mk {
 
-int run_blind_rotate(mk_ctx *ctx, const uint32_t *abar, uint32_t *acc, size_t count, int steps,
-                     int path, hipStream_t s);
-
 namespace {
 
 struct CircDesc {
@@ -446,8 +443,7 @@ int enqueue_run(mk_ctx *ctx, const CircuitRun &R, uint32_t *gate_scratch, const 
             }
             if (hipGetLastError() != hipSuccess) return fail(MK_EDEVICE, "circuit precombine launch failed");
             uint32_t *dst = R.wires + ((size_t)P.level_base[l] * batch + c0) * stride;
-            if ((rc = run_blind_rotate(ctx, abar, acc, cnt, Pm.k * Pm.n, R.path, s)) ||
-                (rc = run_key_switch(ctx, acc, dst, cnt, stride, R.path, s)) ||
+            if ((rc = run_rotate_ks(ctx, abar, acc, dst, cnt, stride, R.path, s)) ||
                 (rc = capture_checkpoint(ctx, s, kChunkKernels)))
                 return rc;
         }

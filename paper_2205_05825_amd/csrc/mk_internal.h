@@ -79,6 +79,9 @@ struct DeviceKeys {
     int8_t xmap[16] = {};
     uint32_t *status = nullptr;
     int rot_kind = -1;
+    // Extraction and key switching inside the persistent rotation's launch
+    // (mk_set_ks_fusion): 1 on, 0 separate kernels.
+    int ks_fuse = 1;
 };
 
 }  // namespace mk

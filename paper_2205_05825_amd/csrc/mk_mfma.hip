@@ -37,6 +37,7 @@
 #include <algorithm>
 
 #include "mk_device_common.h"
+#include "mk_ks_core.h"
 #include "mk_mfma_core.h"
 
 namespace mk {
@@ -787,7 +788,7 @@ static int join_parts(mk_ctx *ctx, int parts, hipStream_t s, hipStream_t *ss) {
 }
 
 int launch_br_mfma(mk_ctx *ctx, const uint32_t *abar, uint32_t *acc_out, size_t count, int steps,
-                   hipStream_t s) {
+                   hipStream_t s, uint32_t *ks_out, size_t ks_stride, bool *ks_done) {
     const mk_params &P = ctx->p;
     Split sp = split_for(ctx, count);
     // per-kernel timing and graph capture see a single stream
@@ -805,9 +806,18 @@ int launch_br_mfma(mk_ctx *ctx, const uint32_t *abar, uint32_t *acc_out, size_t 
     if (persist) {
         hipLaunchKernelGGL(mfma_init_kernel, dim3(blocks((size_t)a[0].GP * K1 * N, 256)), dim3(256), 0, s, a[0]);
         MK_HIP(hipGetLastError(), "mfma init launch");
+        // extraction and key switching inside the launch: each team runs
+        // them on its own tiles right after their last CMux step
+        const bool fuse = ks_out && ks_done && ctx->dev.ks_fuse && ctx->dev.ks_win && steps == P.k * P.n;
+        KsFused kf;
+        if (fuse && (rc = ks_fused_args(ctx, count, ks_out, ks_stride, s, &kf))) return rc;
         {
             StageTimer tp(ctx, 4, s);
-            if ((rc = launch_persist(ctx, a[0], steps, ctl_of(a[0]), s))) return rc;
+            if ((rc = launch_persist(ctx, a[0], steps, ctl_of(a[0]), fuse ? &kf : nullptr, s))) return rc;
+        }
+        if (fuse) {
+            *ks_done = true;
+            return MK_OK;
         }
         const size_t words = count * K1 * N;
         hipLaunchKernelGGL(mfma_copyout_kernel, dim3(blocks(words, 256)), dim3(256), 0, s, a[0].acc, acc_out,

@@ -24,6 +24,10 @@
 // with the evaluation key (b_0 = -a, b_1..b_k), in the same order as the
 // stream-ordered kernels, hence bit-identical to them.  When an XCD owns
 // more tiles than teams fit on it, a team runs c tiles, phase by phase.
+// After the last step a gate launch can also run sample extraction and key
+// switching (§3.2 MKKeySwitch) on the team's tiles: rounding units, one
+// barrier, then the one-hot int8 GEMM tasks (mk_ks_core.h), so the final
+// accumulators never leave the XCD's L2 before they are switched.
 //
 // Teams are pinned to one XCD: a workgroup reads the XCD it runs on from
 // the hardware (XCC_ID), registers there, and forms teams with the
@@ -48,6 +52,7 @@
 #include <vector>
 
 #include "mk_device_common.h"
+#include "mk_ks_core.h"
 #include "mk_mfma_core.h"
 
 namespace mk {
@@ -89,6 +94,7 @@ struct PersistArgs {
     int steps;           // CMux steps run
     int8_t xmap[16];     // XCC_ID -> dense XCD index, -1 if unused
     uint32_t spin_limit;
+    KsFused ks;          // key switching after the last step (ks.tiles != nullptr)
 };
 
 __device__ __forceinline__ uint32_t ld_dev(const uint32_t *p) {
@@ -447,6 +453,28 @@ __global__ __launch_bounds__(kPThreads, PersistCfg<NB>::OCC) void persist_rotati
             if (!team_sync(p, ctr, target, &sh[0])) return;
         }
     }
+    if (!p.ks.tiles) return;
+    // Extraction and key switching of the team's tiles, whose accumulators
+    // are final after the last barrier: rounding units (tile, party, 64
+    // coefficients), one barrier, then GEMM tasks (tile, party, column
+    // block), both spread over the members.  The accumulators and the
+    // rounded coefficients were written by other members, so they are read
+    // with device-scope loads.
+    const KsShape &ks = p.ks.s;
+    const int QB = (ks.N + 63) / 64, units = ks.k * QB;
+    for (int u = r; u < c * units; u += S)
+        ks_round_unit<true>(p.m.acc, ks, p.ks.count, p.ks.R, p.ks.out, p.ks.stride,
+                            x + (tile0 + u / units) * p.nx, (u % units % QB) * 64, u % units / QB, smem);
+    target += S;
+    if (!team_sync(p, ctr, target, &sh[0])) return;
+    const int CB = ks_col_blocks(ks), tasks = ks.k * CB;
+    for (int u = r; u < c * tasks; u += S) {
+        const int gt = x + (tile0 + u / tasks) * p.nx, cb = u % tasks % CB, i = u % tasks / CB;
+        if (ks.lb == 2) ks_gemm_task<true, kCoherent>(p.ks.tiles, p.ks.R, ks, p.ks.count, p.ks.out, p.ks.stride,
+                                                      gt, cb, i, red);
+        else ks_gemm_task<false, kCoherent>(p.ks.tiles, p.ks.R, ks, p.ks.count, p.ks.out, p.ks.stride, gt, cb,
+                                            i, red);
+    }
 }
 
 __global__ void zero_words_kernel(uint32_t *p, int n) {
@@ -500,8 +528,9 @@ template <int NB>
 static int launch_nb(mk_ctx *ctx, PersistArgs &pa, hipStream_t s) {
     const DeviceKeys &D = ctx->dev;
     auto kern = persist_rotation_kernel<NB>;
-    const size_t lds = std::max<size_t>((size_t)kMaxRUnits * kRGates * NB * 32 * 4,
-                                        (size_t)PersistCfg<NB>::MR * kLimbTileBytes);
+    const size_t lds = std::max<size_t>({(size_t)kMaxRUnits * kRGates * NB * 32 * 4,
+                                         (size_t)PersistCfg<NB>::MR * kLimbTileBytes, (size_t)kKsRoundLds,
+                                         (size_t)kKsGemmLds});
     if (lds > 65536)
         MK_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
                "persistent rotation LDS attribute");
@@ -525,8 +554,9 @@ static int launch_nb(mk_ctx *ctx, PersistArgs &pa, hipStream_t s) {
 }
 
 // Runs CMux steps 0 .. steps-1 of the batch described by `m` (accumulator
-// already initialised) as one persistent launch.
-int launch_persist(mk_ctx *ctx, const MfmaArgs &m, int steps, uint32_t *ctl, hipStream_t s) {
+// already initialised) as one persistent launch; with `ks`, the whole
+// rotation followed by extraction and key switching into ks->out.
+int launch_persist(mk_ctx *ctx, const MfmaArgs &m, int steps, uint32_t *ctl, const KsFused *ks, hipStream_t s) {
     const mk_params &P = ctx->p;
     DeviceKeys &D = ctx->dev;
     if (!persist_supported(P)) return fail(MK_EPARAM, "persistent rotation: parameters out of range");
@@ -540,6 +570,12 @@ int launch_persist(mk_ctx *ctx, const MfmaArgs &m, int steps, uint32_t *ctl, hip
     pa.steps = steps;
     std::memcpy(pa.xmap, D.xmap, sizeof(pa.xmap));
     pa.spin_limit = 1u << 24;
+    std::memset(&pa.ks, 0, sizeof(pa.ks));
+    if (ks) {
+        if (steps != P.k * P.n || ks->count != (size_t)m.G)
+            return fail(MK_EINTERNAL, "fused key switching needs the whole rotation of the batch");
+        pa.ks = *ks;
+    }
     const int words = (int)persist_ctl_words(m.GP / 32);
     hipLaunchKernelGGL(zero_words_kernel, dim3((words + 255) / 256), dim3(256), 0, s, ctl, words);
     MK_HIP(hipGetLastError(), "persistent control clear");
@@ -562,6 +598,12 @@ int mk_set_rotation(mk_ctx *ctx, int kind) {
     if (!ctx || kind < MK_ROT_AUTO || kind > MK_ROT_PERSISTENT)
         return fail(MK_EINVAL, "mk_set_rotation: bad argument");
     ctx->dev.rot_kind = kind;
+    return MK_OK;
+}
+
+int mk_set_ks_fusion(mk_ctx *ctx, int on) {
+    if (!ctx || (on != 0 && on != 1)) return fail(MK_EINVAL, "mk_set_ks_fusion: bad argument");
+    ctx->dev.ks_fuse = on;
     return MK_OK;
 }
 

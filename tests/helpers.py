@@ -16,7 +16,7 @@ from oracle import tfhe
 
 FIELDS = ("k", "n", "N", "bk_ell", "ks_t", "bk_noise_log2", "ks_noise_log2",
           "lwe_noise_log2", "bk_log_base", "ks_log_base")
-SEEDS = {"C1": 0, "C1B": 5, "C1B4": 6, "C1S": 7, "C2": 2, "C3": 3, "C8": 11, "TOY": 9, "TOYB3": 10}
+SEEDS = {"C1": 0, "C1B": 5, "C1B4": 6, "C1S": 7, "C2": 2, "C3": 3, "C8": 11, "TOY": 9, "TOYB3": 10, "C1SB3": 12}
 HEADER_BYTES = 4 + 4 + 40 + 4
 
 

@@ -21,17 +21,19 @@ def torch_cuda():
     return torch
 
 
-def _gates(torch, ctx, types, c1, c2, rot):
+def _gates(torch, ctx, types, c1, c2, rot, fuse=True):
     d = torch.device("cuda:0")
     t = torch.from_numpy(np.ascontiguousarray(types, np.uint8)).to(d)
     a = torch.from_numpy(np.ascontiguousarray(c1).view(np.int32)).to(d)
     b = torch.from_numpy(np.ascontiguousarray(c2).view(np.int32)).to(d)
     out = torch.full_like(a, -1)
     ctx.set_rotation(rot)
+    ctx.set_ks_fusion(fuse)
     try:
         ctx.bootstrap_gate(t, a, b, out, path=1)
     finally:
         ctx.set_rotation(-1)
+        ctx.set_ks_fusion(True)
     torch.cuda.synchronize()
     ctx.device_status()
     return out.cpu().numpy().view(np.uint32)
@@ -59,18 +61,40 @@ def _workload(K, cnt, seed):
     return types, m1, m2, c1, c2
 
 
-@pytest.mark.parametrize("name,cnt", [("C1B", 70), ("C1S", 45), ("C1B4", 97), ("C1B", 1)])
+@pytest.mark.parametrize("name,cnt", [("C1B", 70), ("C1S", 45), ("C1B4", 97), ("C1SB3", 75), ("C1B", 1)])
 def test_gates_every_word(torch_cuda, name, cnt):
-    """Whole gates with the persistent rotation forced: every output word
-    equals the oracle's (N = 256 and N = 128 rings, k = 2 and k = 4 parties,
-    ragged gate tiles, a single gate) and decrypts to the plaintext gate
-    (the C1B noise levels make every gate decrypt; C1's do not)."""
+    """Whole gates with the persistent rotation forced (extraction and key
+    switching inside its launch): every output word equals the oracle's
+    (N = 256 and N = 128 rings, k = 2, 3 and 4 parties, base-4 and base-8
+    key switching, ragged gate tiles, a single gate) and decrypts to the
+    plaintext gate (the C1B noise levels make every gate decrypt; C1's do
+    not)."""
     K, ctx = helpers.gpu_world(name)
     types, m1, m2, c1, c2 = _workload(K, cnt, 60 + cnt)
     got = _gates(torch_cuda, ctx, types, c1, c2, PERSISTENT)
     assert np.array_equal(got, helpers.oracle_gates(name, types, c1, c2))
     want = [mi.plain_gate(int(t), int(a), int(b)) for t, a, b in zip(types, m1, m2)]
     assert tfhe.decrypt(K, got).tolist() == want
+
+
+@pytest.mark.parametrize("name,cnt", [("C1SB3", 300), ("C1B", 1100), ("C2", 1100)])
+def test_fused_key_switch(torch_cuda, name, cnt):
+    """Extraction and key switching inside the persistent launch give the
+    same words as the separate kernels after it and as the stream-ordered
+    schedule; three gates equal the oracle's and every gate decrypts.  At
+    the Table 7 shape 1100 gates are 35 tiles, more than the 4 teams an XCD
+    holds at once, so teams switch two tiles each."""
+    K, ctx = helpers.gpu_world(name)
+    types, m1, m2, c1, c2 = _workload(K, cnt, 80 + cnt)
+    fused = _gates(torch_cuda, ctx, types, c1, c2, PERSISTENT)
+    apart = _gates(torch_cuda, ctx, types, c1, c2, PERSISTENT, fuse=False)
+    strm = _gates(torch_cuda, ctx, types, c1, c2, STREAM)
+    assert np.array_equal(fused, apart)
+    assert np.array_equal(fused, strm)
+    idx = [0, cnt // 2, cnt - 1]
+    assert np.array_equal(fused[idx], helpers.oracle_gates(name, types, c1, c2, idx))
+    want = [mi.plain_gate(int(t), int(a), int(b)) for t, a, b in zip(types, m1, m2)]
+    assert tfhe.decrypt(K, fused).tolist() == want
 
 
 @pytest.mark.parametrize("name,cnt,steps", [("C2", 200, 600), ("C2", 1061, 40), ("C3", 97, 600),

@@ -135,6 +135,24 @@ def test_tile_shape_arguments():
     assert e.value.code == -4
 
 
+def test_schedule_switch_arguments():
+    """Rotation schedule and key-switch fusion setters take their documented
+    values only (host checks, no device work)."""
+    import paper_2205_05825_amd as mk
+    ctx = mk.Context(helpers.lib_params(OP.C1), 3)
+    for kind in (mk.ROT_AUTO, mk.ROT_STREAM, mk.ROT_PERSISTENT):
+        ctx.set_rotation(kind)
+    for on in (False, True):
+        ctx.set_ks_fusion(on)
+    for bad in (-2, 2):
+        with pytest.raises(mk.MkError) as e:
+            ctx.set_rotation(bad)
+        assert e.value.code == -1
+    from paper_2205_05825_amd import _lib
+    assert _lib._L.mk_set_ks_fusion(ctx._h, 2) == -1
+    assert _lib._L.mk_set_ks_fusion(None, 1) == -1
+
+
 def test_builder_and_parameter_limits():
     """Argument checks on the host: netlist builder ranges, the party limit,
     and the int8 exactness bound (k+1)*ell*N*2^14 < 2^31, which the
