@@ -405,9 +405,11 @@ int mk_get_tiles(const mk_ctx *ctx, size_t count, int32_t *gemm1_shape,
  *                      workgroups runs it, meeting at a barrier after each
  *                      phase of a CMux step (rotate + decompose, stage 1,
  *                      stage 2).  Needs N in {128, 256, 512, 1024, 2048}.
- *   MK_ROT_AUTO        the persistent schedule for batches of at least 2.5
- *                      tiles per XCD (640 gates on MI355X), where it is
- *                      faster; stream-ordered kernels below (default).
+ *   MK_ROT_AUTO        the persistent schedule where it is faster: at
+ *                      N = 1024 for batches of at least one tile per XCD
+ *                      (256 gates on MI355X), with teams sized to the batch
+ *                      (mk_set_team_rows), at other N from 2.5 tiles per
+ *                      XCD; stream-ordered kernels below (default).
  * Errors: MK_EINVAL. */
 #define MK_ROT_AUTO -1
 #define MK_ROT_STREAM 0
@@ -421,6 +423,18 @@ int mk_set_rotation(mk_ctx *ctx, int kind);
  * after the launch (the only form after stream-ordered rotations).  Results
  * are identical either way.  Errors: MK_EINVAL. */
 int mk_set_ks_fusion(mk_ctx *ctx, int on);
+
+/* Team size of the persistent rotation at N = 1024: each 32-gate tile is
+ * run by 2 * 32 / rows workgroups, each contracting `rows` 32-row tiles per
+ * task.  rows = 0 (default) picks by batch width: 2 (teams of 32, a whole
+ * XCD per tile) when no XCD has more than one tile, 4 (teams of 16) at two
+ * tiles per XCD, 8 (teams of 8, the most MFMAs per key tile loaded) from
+ * three on.  rows = 2, 4 or 8 forces that size (tuning and tests).  Every
+ * size gives the same words.  mk_get_team_rows reports the size a batch of
+ * `count` gates runs with (also at other N, where it is fixed).
+ * Errors: MK_EINVAL (other values, or rows != 0 at N != 1024). */
+int mk_set_team_rows(mk_ctx *ctx, int rows);
+int mk_get_team_rows(const mk_ctx *ctx, size_t count, int32_t *rows);
 
 /* Waits for `stream`, then reports and clears the context's device status
  * word, which device entry points set when they meet a condition they can

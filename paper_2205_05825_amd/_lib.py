@@ -103,6 +103,8 @@ _SIGS = {
     "mk_get_tiles": ([_vp, _sz, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], _i),
     "mk_set_rotation": ([_vp, _i], _i),
     "mk_set_ks_fusion": ([_vp, _i], _i),
+    "mk_set_team_rows": ([_vp, _i], _i),
+    "mk_get_team_rows": ([_vp, _sz, ctypes.POINTER(ctypes.c_int32)], _i),
     "mk_device_status": ([_vp, _vp], _i),
     "mk_set_profiling": ([_vp, _i], _i),
     "mk_get_profile": ([_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), _i], _i),
@@ -302,6 +304,16 @@ class Context:
         """Extraction and key switching inside the persistent rotation's
         launch (True, default) or as separate kernels after it (False)."""
         _check(_L.mk_set_ks_fusion(self._h, int(bool(on))))
+
+    def set_team_rows(self, rows: int = 0):
+        """Row tiles per task of the persistent rotation at N = 1024 (2, 4 or
+        8; 0 = chosen by batch width)."""
+        _check(_L.mk_set_team_rows(self._h, int(rows)))
+
+    def get_team_rows(self, count: int) -> int:
+        r = ctypes.c_int32()
+        _check(_L.mk_get_team_rows(self._h, int(count), ctypes.byref(r)))
+        return r.value
 
     def device_status(self, stream=None):
         """Waits for the stream; raises MkError if a persistent rotation gave

@@ -54,6 +54,7 @@ struct KsFused;
 int persist_probe(mk_ctx *ctx, hipStream_t s);
 size_t persist_ctl_words(int GT);
 bool persist_supported(const mk_params &P);
+int persist_team_rows(const mk_ctx *ctx, int GT);
 int launch_persist(mk_ctx *ctx, const MfmaArgs &m, int steps, uint32_t *ctl, const KsFused *ks, hipStream_t s);
 // Key switching as an int8-MFMA GEMM (mk_keyswitch.hip).
 size_t ks_scratch_need(const mk_params &P, size_t count);

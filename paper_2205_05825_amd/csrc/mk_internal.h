@@ -82,6 +82,9 @@ struct DeviceKeys {
     // Extraction and key switching inside the persistent rotation's launch
     // (mk_set_ks_fusion): 1 on, 0 separate kernels.
     int ks_fuse = 1;
+    // Row tiles per contraction task of the persistent rotation at N = 1024
+    // (mk_set_team_rows): 0 chosen by batch width, else 2, 4 or 8.
+    int team_rows = 0;
 };
 
 }  // namespace mk

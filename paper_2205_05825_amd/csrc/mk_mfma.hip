@@ -596,15 +596,20 @@ static uint32_t *ctl_of(const MfmaArgs &a) {
 }
 
 // Whether the persistent rotation runs a batch of GT gate tiles: by choice
-// (mk_set_rotation), else from 2.5 tiles per XCD on.  Measured on MI355X at
-// the Table 7 shape (persistent against stream-ordered): 256 gates 71 / 50
-// ms, 512 gates 73 / 72, 640 gates 75 / 81, 768 gates 78 / 91, 1024 gates
-// 88 / 100 (with fewer tiles a team of 8 CUs per tile leaves most of the
-// chip idle, while the stream-ordered kernels split a tile over many CUs).
+// (mk_set_rotation), else at N = 1024 from one tile per XCD on (the team
+// size then follows the batch width, persist_team_rows), and at other N from
+// 2.5 tiles per XCD on.  Measured on MI355X at the Table 7 shape, stream-
+// ordered against persistent (ms per batch, team size in brackets): 128
+// gates 37.8 / 49.4 (32), 256 gates 50.6 / 45.6 (32), 384 gates 66.5 / 53.0
+// (16), 512 gates 72.9 / 58.8 (16), 640 gates 81.7 / 76.6 (8), 768 gates
+// 92.4 / 79.4 (8), 1024 gates 101.6 / 88.0 (8).  Below one tile per XCD
+// whole XCDs would idle, while the stream-ordered kernels split a tile over
+// many compute units.
 static bool use_persist(const mk_ctx *ctx, int GT) {
     const DeviceKeys &D = ctx->dev;
     if (D.rot_kind == MK_ROT_STREAM || D.num_xcd <= 0 || !persist_supported(ctx->p)) return false;
-    return D.rot_kind == MK_ROT_PERSISTENT || 2 * GT >= 5 * D.num_xcd;
+    if (D.rot_kind == MK_ROT_PERSISTENT) return true;
+    return ctx->p.N == 1024 ? GT >= D.num_xcd : 2 * GT >= 5 * D.num_xcd;
 }
 
 // Sub-batches of a rotation: a batch can be split in two halves that run on

@@ -73,16 +73,22 @@ constexpr int kRGates = 4;         // gates per R unit
 constexpr int kMaxRUnits = 4;      // R units held in LDS at once
 constexpr int kLimbTileBytes = 4 * 4 * 64 * 16;     // one row tile's four limbs in LDS
 
-// Row block, prefetch depth and workgroups per compute unit of the
-// contraction for N = 32 NB (the rings of the seamless schedule must divide
-// NB, see slide_gemm).
-template <int NB>
+// Prefetch depths and workgroups per compute unit of the contraction for
+// N = 32 NB with row blocks of MR row tiles (team size S = 2 NB / MR; the
+// rings of the seamless schedule must divide NB, see slide_gemm).  At N =
+// 1024 three team sizes are built: MR = 8 (S = 8) for batches of at least
+// three tiles per XCD, and MR = 4 (S = 16) and MR = 2 (S = 32) so that
+// narrower batches still spread each tile over most of an XCD's compute
+// units.
+template <int NB, int MR>
 struct PersistCfg;
-template <> struct PersistCfg<4> { static constexpr int MR = 2, D = 2, OCC = 2, PF = 2; };
-template <> struct PersistCfg<8> { static constexpr int MR = 4, D = 4, OCC = 2, PF = 4; };
-template <> struct PersistCfg<16> { static constexpr int MR = 4, D = 4, OCC = 2, PF = 4; };
-template <> struct PersistCfg<32> { static constexpr int MR = 8, D = 6, OCC = 1, PF = 10; };
-template <> struct PersistCfg<64> { static constexpr int MR = 8, D = 6, OCC = 1, PF = 4; };
+template <> struct PersistCfg<4, 2> { static constexpr int D = 2, OCC = 2, PF = 2; };
+template <> struct PersistCfg<8, 4> { static constexpr int D = 4, OCC = 2, PF = 4; };
+template <> struct PersistCfg<16, 4> { static constexpr int D = 4, OCC = 2, PF = 4; };
+template <> struct PersistCfg<32, 8> { static constexpr int D = 6, OCC = 1, PF = 10; };
+template <> struct PersistCfg<32, 4> { static constexpr int D = 6, OCC = 1, PF = 10; };
+template <> struct PersistCfg<32, 2> { static constexpr int D = 6, OCC = 1, PF = 10; };
+template <> struct PersistCfg<64, 8> { static constexpr int D = 6, OCC = 1, PF = 4; };
 
 struct PersistArgs {
     MfmaArgs m;
@@ -299,10 +305,11 @@ __device__ __forceinline__ void store_v_digits(const MfmaArgs &a, int tile, int 
 // c'_j into ACC_j for every live slot j (one seamless stream of live x ell
 // polynomials, one segment per slot), 1 = w into V, 2 = stage-2 unit o into
 // ACC_{o ? 1+party : 0}.
-template <int NB>
+template <int NB, int MR>
 __device__ __forceinline__ void task_gemm(const PersistArgs &p, int kind, int j_or_o, int t, int rb, int party,
                                           int bit, int live, uint4 *red) {
-    constexpr int MR = PersistCfg<NB>::MR, ND = 2 * NB - 1;
+    constexpr int ND = 2 * NB - 1;
+    using Cfg = PersistCfg<NB, MR>;
     const MfmaArgs &a = p.m;
     const int N = a.N, K1 = a.k + 1, ell = a.ell, GT = a.GP / 32;
     const int lane = threadIdx.x & 63;
@@ -337,7 +344,7 @@ __device__ __forceinline__ void task_gemm(const PersistArgs &p, int kind, int j_
         // barrier before the first put keeps a segment's puts clear of the
         // previous segment's reads.
         uint4 *slots = red;
-        slide_gemm_seg<MR, NB, PersistCfg<NB>::D, kCoherent, PersistCfg<NB>::PF>(
+        slide_gemm_seg<MR, NB, Cfg::D, kCoherent, Cfg::PF>(
             o, ell, w, lane, acc,
             [&](int r, int s) { return ld_coherent(racc, (lane_word + (uint32_t)(s * N + 32 * r)) * 4u); },
             [&](int r) {
@@ -387,7 +394,7 @@ __device__ __forceinline__ void task_gemm(const PersistArgs &p, int kind, int j_
     // and turned into limb seeds (registers only) once those are in flight
     const bool seed = kind != 1 && (w == 0 || w == 3);
     if (seed) load_old_coherent<MR>(rbase, gate_stride, rb, lane, acc);
-    slide_gemm<MR, NB, PersistCfg<NB>::D, kCoherent>(o, w, lane, acc, [&]() {
+    slide_gemm<MR, NB, Cfg::D, kCoherent>(o, w, lane, acc, [&]() {
         if (seed) seed_old<MR, 1>(w, acc);
     });
     uint4 sum[MR];
@@ -397,15 +404,15 @@ __device__ __forceinline__ void task_gemm(const PersistArgs &p, int kind, int j_
     __syncthreads();   // red is reused by the next task
 }
 
-template <int NB>
-__global__ __launch_bounds__(kPThreads, PersistCfg<NB>::OCC) void persist_rotation_kernel(PersistArgs p) {
+template <int NB, int MR>
+__global__ __launch_bounds__(kPThreads, (PersistCfg<NB, MR>::OCC)) void persist_rotation_kernel(PersistArgs p) {
     // R units keep their accumulator rows here, contraction tasks their limb
     // combination buffer; a workgroup runs one at a time
     extern __shared__ __align__(16) uint32_t smem[];
     uint32_t *rows = smem;
     uint4 *red = reinterpret_cast<uint4 *>(smem);
     __shared__ int sh[2];
-    constexpr int MR = PersistCfg<NB>::MR, RB = NB / MR, S = 2 * RB;
+    constexpr int RB = NB / MR, S = 2 * RB;
     const int GT = p.m.GP / 32;
     if (threadIdx.x == 0) {
         const int xcc = __builtin_amdgcn_s_getreg((31 << 11) | 20) & 15;  // HW_REG_XCC_ID
@@ -447,7 +454,7 @@ __global__ __launch_bounds__(kPThreads, PersistCfg<NB>::OCC) void persist_rotati
                 const int kind = ph == 2 ? 2 : (r < RB ? 1 : 0);
                 const int jo = ph == 2 ? r / RB : 0;
                 const int rb = ph == 2 ? r % RB : (r < RB ? r : r - RB);
-                task_gemm<NB>(p, kind, jo, x + (tile0 + ti) * p.nx, rb, party, bit, L, red);
+                task_gemm<NB, MR>(p, kind, jo, x + (tile0 + ti) * p.nx, rb, party, bit, L, red);
             }
             target += S;
             if (!team_sync(p, ctr, target, &sh[0])) return;
@@ -516,6 +523,25 @@ int persist_probe(mk_ctx *ctx, hipStream_t s) {
     return MK_OK;
 }
 
+// Row tiles per contraction task (MR) of the persistent rotation of GT gate
+// tiles: forced by mk_set_team_rows, else, at N = 1024, the smallest team
+// that keeps every compute unit of an XCD busy.  An XCD with 1 or 2 tiles
+// runs teams of 32 (MR = 2) or 16 (MR = 4) workgroups, from 3 tiles on
+// teams of 8 (MR = 8, the most MFMAs per key tile).  Other rings have one
+// size.
+int persist_team_rows(const mk_ctx *ctx, int GT) {
+    const mk_params &P = ctx->p;
+    const DeviceKeys &D = ctx->dev;
+    const int NB = P.N / 32;
+    if (NB != 32) return NB == 4 ? 2 : NB == 64 ? 8 : 4;
+    if (D.team_rows) return D.team_rows;
+    const int nx = std::max(1, D.num_xcd), cus = D.num_cus / nx;
+    const int ntx = (GT + nx - 1) / nx;
+    if (ntx <= 1 && cus >= 32) return 2;
+    if (ntx <= 2 && cus >= 16) return 4;
+    return 8;
+}
+
 // Teams number at most the tiles plus one per XCD.
 size_t persist_ctl_words(int GT) { return (size_t)kCtlHeader + (size_t)(GT + 16) * kCtlPerTeam; }
 
@@ -524,21 +550,20 @@ bool persist_supported(const mk_params &P) {
     return (NB == 4 || NB == 8 || NB == 16 || NB == 32 || NB == 64) && P.bk_ell <= kMaxEll;
 }
 
-template <int NB>
+template <int NB, int MR>
 static int launch_nb(mk_ctx *ctx, PersistArgs &pa, hipStream_t s) {
     const DeviceKeys &D = ctx->dev;
-    auto kern = persist_rotation_kernel<NB>;
-    const size_t lds = std::max<size_t>({(size_t)kMaxRUnits * kRGates * NB * 32 * 4,
-                                         (size_t)PersistCfg<NB>::MR * kLimbTileBytes, (size_t)kKsRoundLds,
-                                         (size_t)kKsGemmLds});
+    auto kern = persist_rotation_kernel<NB, MR>;
+    const size_t lds = std::max<size_t>({(size_t)kMaxRUnits * kRGates * NB * 32 * 4, (size_t)MR * kLimbTileBytes,
+                                         (size_t)kKsRoundLds, (size_t)kKsGemmLds});
     if (lds > 65536)
         MK_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
                "persistent rotation LDS attribute");
     int occ = 0;
     MK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)kern, kPThreads, lds),
            "persistent rotation occupancy");
-    occ = std::max(1, std::min(occ, PersistCfg<NB>::OCC));
-    constexpr int S = 2 * (NB / PersistCfg<NB>::MR);
+    occ = std::max(1, std::min(occ, PersistCfg<NB, MR>::OCC));
+    constexpr int S = 2 * (NB / MR);
     const int per_xcd = occ * (D.num_cus / D.num_xcd);   // workgroups an XCD holds at once
     if (S > per_xcd) return fail(MK_EPARAM, "persistent rotation: a team does not fit on one XCD");
     const int GT = pa.m.GP / 32;
@@ -580,11 +605,16 @@ int launch_persist(mk_ctx *ctx, const MfmaArgs &m, int steps, uint32_t *ctl, con
     hipLaunchKernelGGL(zero_words_kernel, dim3((words + 255) / 256), dim3(256), 0, s, ctl, words);
     MK_HIP(hipGetLastError(), "persistent control clear");
     switch (P.N / 32) {
-        case 4: return launch_nb<4>(ctx, pa, s);
-        case 8: return launch_nb<8>(ctx, pa, s);
-        case 16: return launch_nb<16>(ctx, pa, s);
-        case 32: return launch_nb<32>(ctx, pa, s);
-        default: return launch_nb<64>(ctx, pa, s);
+        case 4: return launch_nb<4, 2>(ctx, pa, s);
+        case 8: return launch_nb<8, 4>(ctx, pa, s);
+        case 16: return launch_nb<16, 4>(ctx, pa, s);
+        case 32:
+            switch (persist_team_rows(ctx, m.GP / 32)) {
+                case 2: return launch_nb<32, 2>(ctx, pa, s);
+                case 4: return launch_nb<32, 4>(ctx, pa, s);
+                default: return launch_nb<32, 8>(ctx, pa, s);
+            }
+        default: return launch_nb<64, 8>(ctx, pa, s);
     }
 }
 
@@ -598,6 +628,20 @@ int mk_set_rotation(mk_ctx *ctx, int kind) {
     if (!ctx || kind < MK_ROT_AUTO || kind > MK_ROT_PERSISTENT)
         return fail(MK_EINVAL, "mk_set_rotation: bad argument");
     ctx->dev.rot_kind = kind;
+    return MK_OK;
+}
+
+int mk_set_team_rows(mk_ctx *ctx, int rows) {
+    if (!ctx || (rows != 0 && rows != 2 && rows != 4 && rows != 8))
+        return fail(MK_EINVAL, "mk_set_team_rows: rows must be 0, 2, 4 or 8");
+    if (rows && ctx->p.N != 1024) return fail(MK_EINVAL, "mk_set_team_rows: team sizes are selectable at N = 1024 only");
+    ctx->dev.team_rows = rows;
+    return MK_OK;
+}
+
+int mk_get_team_rows(const mk_ctx *ctx, size_t count, int32_t *rows) {
+    if (!ctx || !rows) return fail(MK_EINVAL, "mk_get_team_rows: null argument");
+    *rows = persist_team_rows(ctx, (int)((count + 31) / 32));
     return MK_OK;
 }
 

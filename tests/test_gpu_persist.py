@@ -21,7 +21,7 @@ def torch_cuda():
     return torch
 
 
-def _gates(torch, ctx, types, c1, c2, rot, fuse=True):
+def _gates(torch, ctx, types, c1, c2, rot, fuse=True, rows=0):
     d = torch.device("cuda:0")
     t = torch.from_numpy(np.ascontiguousarray(types, np.uint8)).to(d)
     a = torch.from_numpy(np.ascontiguousarray(c1).view(np.int32)).to(d)
@@ -29,26 +29,31 @@ def _gates(torch, ctx, types, c1, c2, rot, fuse=True):
     out = torch.full_like(a, -1)
     ctx.set_rotation(rot)
     ctx.set_ks_fusion(fuse)
+    if rows:
+        ctx.set_team_rows(rows)
     try:
         ctx.bootstrap_gate(t, a, b, out, path=1)
     finally:
         ctx.set_rotation(-1)
         ctx.set_ks_fusion(True)
+        ctx.set_team_rows(0)
     torch.cuda.synchronize()
     ctx.device_status()
     return out.cpu().numpy().view(np.uint32)
 
 
-def _rotate(torch, ctx, abar, steps, rot):
+def _rotate(torch, ctx, abar, steps, rot, rows=0):
     P = ctx.params
     d = torch.device("cuda:0")
     ta = torch.from_numpy(np.ascontiguousarray(abar).view(np.int32)).to(d)
     acc = torch.zeros((len(abar), (P.k + 1) * P.N), dtype=torch.int32, device=d)
     ctx.set_rotation(rot)
+    ctx.set_team_rows(rows)
     try:
         ctx.blind_rotate(ta, acc, max_steps=steps, path=1)
     finally:
         ctx.set_rotation(-1)
+        ctx.set_team_rows(0)
     torch.cuda.synchronize()
     ctx.device_status()
     return acc.cpu().numpy().view(np.uint32)
@@ -95,6 +100,37 @@ def test_fused_key_switch(torch_cuda, name, cnt):
     assert np.array_equal(fused[idx], helpers.oracle_gates(name, types, c1, c2, idx))
     want = [mi.plain_gate(int(t), int(a), int(b)) for t, a, b in zip(types, m1, m2)]
     assert tfhe.decrypt(K, fused).tolist() == want
+
+
+@pytest.mark.parametrize("rows", [2, 4, 8])
+def test_team_sizes_match_stream(torch_cuda, rows):
+    """Every team size of the persistent rotation at the Table 7 shape (32,
+    16 and 8 workgroups per tile) gives the stream-ordered schedule's words
+    on 300 gates (10 tiles, a ragged last one: one or two per XCD, so with
+    teams of 32 one team runs two tiles), with key switching fused; sampled
+    gates equal the oracle's and every gate decrypts."""
+    K, ctx = helpers.gpu_world("C2")
+    types, m1, m2, c1, c2 = _workload(K, 300, 77)
+    per = _gates(torch_cuda, ctx, types, c1, c2, PERSISTENT, rows=rows)
+    strm = _gates(torch_cuda, ctx, types, c1, c2, STREAM)
+    assert np.array_equal(per, strm)
+    idx = [0, 299]
+    assert np.array_equal(per[idx], helpers.oracle_gates("C2", types, c1, c2, idx))
+    want = [mi.plain_gate(int(t), int(a), int(b)) for t, a, b in zip(types, m1, m2)]
+    assert tfhe.decrypt(K, per).tolist() == want
+
+
+@pytest.mark.parametrize("rows", [2, 4])
+def test_narrow_teams_partial_rotation(torch_cuda, rows):
+    """Teams of 32 and 16 workgroups over 1061 gates (34 tiles: a team runs
+    up to five tiles phase by phase) for 600 CMux steps, across the party
+    boundary: the same words as the stream-ordered schedule."""
+    K, ctx = helpers.gpu_world("C2")
+    P = K.params
+    abar = np.random.default_rng(rows).integers(0, 2 * P.N, (1061, P.lwe_words)).astype(np.uint32)
+    per = _rotate(torch_cuda, ctx, abar, 600, PERSISTENT, rows=rows)
+    strm = _rotate(torch_cuda, ctx, abar, 600, STREAM)
+    assert np.array_equal(per, strm)
 
 
 @pytest.mark.parametrize("name,cnt,steps", [("C2", 200, 600), ("C2", 1061, 40), ("C3", 97, 600),
