@@ -505,15 +505,25 @@ int run_key_switch(mk_ctx *ctx, const uint32_t *acc, uint32_t *out, size_t count
 
 int run_rotate_ks(mk_ctx *ctx, const uint32_t *abar, uint32_t *acc, uint32_t *out, size_t count, size_t stride,
                   int path, hipStream_t s) {
+    const mk_params &P = ctx->p;
+    const int steps = P.k * P.n;
     int rc;
-    if (path == MK_PATH_MFMA_I8) {
-        bool done = false;
-        if ((rc = launch_br_mfma(ctx, abar, acc, count, ctx->p.k * ctx->p.n, s, out, stride, &done)) || done)
-            return rc;
-    } else if ((rc = run_blind_rotate(ctx, abar, acc, count, ctx->p.k * ctx->p.n, path, s))) {
-        return rc;
+    if (path != MK_PATH_MFMA_I8) {
+        if ((rc = run_blind_rotate(ctx, abar, acc, count, steps, path, s))) return rc;
+        return run_key_switch(ctx, acc, out, count, stride, path, s);
     }
-    return run_key_switch(ctx, acc, out, count, stride, path, s);
+    // one or two consecutive launches (mfma_rotation_split)
+    const size_t first = mfma_rotation_split(ctx, count);
+    for (size_t off = 0; off < count;) {
+        const size_t n = off ? count - off : first;
+        const uint32_t *ab = abar + off * lwe_words(P);
+        uint32_t *ac = acc + off * (size_t)(P.k + 1) * P.N, *o = out + off * stride;
+        bool done = false;
+        if ((rc = launch_br_mfma(ctx, ab, ac, n, steps, s, o, stride, &done))) return rc;
+        if (!done && (rc = run_key_switch(ctx, ac, o, n, stride, path, s))) return rc;
+        off += n;
+    }
+    return MK_OK;
 }
 
 // Gates per rotation launch: larger batches (and wide circuit levels) run in

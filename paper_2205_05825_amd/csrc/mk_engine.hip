@@ -406,9 +406,10 @@ __global__ void copy_words_kernel(const uint32_t *__restrict__ src, uint32_t *__
 }
 
 // Kernels of one chunk of a level outside the stepwise rotation (which
-// reports its own): pre-combination, accumulator set-up and copies of the
-// persistent rotation, extraction and key switching, with some margin.
-constexpr int kChunkKernels = 8;
+// reports its own): pre-combination, and for each of up to two rotation
+// launches the accumulator set-up, control clear, persistent launch, copies,
+// extraction and key switching, with some margin.
+constexpr int kChunkKernels = 16;
 
 // Device work of one evaluation, kernels only (so that it can be captured
 // into a graph): inputs into their wire slots, every level's

@@ -612,6 +612,28 @@ static bool use_persist(const mk_ctx *ctx, int GT) {
     return ctx->p.N == 1024 ? GT >= D.num_xcd : 2 * GT >= 5 * D.num_xcd;
 }
 
+// Gates of the first part when an automatic persistent rotation of `count`
+// gates is better run as two consecutive launches, else `count`.  At N =
+// 1024 an XCD holds U = (its compute units) / 8 teams of 8 workgroups; with
+// more than U tiles on an XCD some teams run two or more tiles phase by
+// phase.  When the tiles beyond the last full round are at most one per
+// XCD, the batch runs as the full rounds, then the remainder as its own
+// launch (teams of 32, or the stream-ordered kernels below one tile per
+// XCD).  Measured at the Table 7 shape, one launch against two: 1100 gates
+// 139.9 / 127.4 ms, 1280 gates 143.8 / 133.3; with larger remainders one
+// launch is as fast or faster (1536 gates 147.3 / 146.6, 1792 gates
+// 163.1 / 167.5, 2400 gates 225.1 / 228.5), since a team running two
+// tiles pays its barriers and pipeline fills once for both.
+size_t mfma_rotation_split(const mk_ctx *ctx, size_t count) {
+    const DeviceKeys &D = ctx->dev;
+    const int GT = (int)((count + 31) / 32);
+    if (ctx->p.N != 1024 || D.rot_kind != MK_ROT_AUTO || D.team_rows || !use_persist(ctx, GT)) return count;
+    const int round = D.num_xcd * std::max(1, D.num_cus / D.num_xcd / 8);   // tiles of one full round
+    const int rem = GT % round;
+    if (GT <= round || rem == 0 || rem > D.num_xcd) return count;
+    return (size_t)(GT - rem) * 32;
+}
+
 // Sub-batches of a rotation: a batch can be split in two halves that run on
 // two streams, so that one half's memory-bound digit kernels and GEMM tails
 // overlap the other half's GEMMs.  The split is chosen by the autotuner per

@@ -120,6 +120,23 @@ def test_team_sizes_match_stream(torch_cuda, rows):
     assert tfhe.decrypt(K, per).tolist() == want
 
 
+@pytest.mark.parametrize("cnt", [1100, 1280, 1344])
+def test_ragged_wide_batch_split(torch_cuda, cnt):
+    """The automatic schedule on batches just over one full round of teams
+    (32 tiles at the Table 7 shape): 1100 and 1280 gates run 1024 gates on
+    teams of 8, then the remainder as a second launch (76 gates on the
+    stream-ordered kernels, 256 gates on teams of 32); 1344 gates (10 tiles
+    over) stay in one launch.  Every word equals the stream-ordered
+    schedule's for the whole batch, and every gate decrypts."""
+    K, ctx = helpers.gpu_world("C2")
+    types, m1, m2, c1, c2 = _workload(K, cnt, 91)
+    auto = _gates(torch_cuda, ctx, types, c1, c2, -1)
+    strm = _gates(torch_cuda, ctx, types, c1, c2, STREAM)
+    assert np.array_equal(auto, strm)
+    want = [mi.plain_gate(int(t), int(a), int(b)) for t, a, b in zip(types, m1, m2)]
+    assert tfhe.decrypt(K, auto).tolist() == want
+
+
 @pytest.mark.parametrize("rows", [2, 4])
 def test_narrow_teams_partial_rotation(torch_cuda, rows):
     """Teams of 32 and 16 workgroups over 1061 gates (34 tiles: a team runs
