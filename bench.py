@@ -55,7 +55,7 @@ TRAFFIC = {
                 [os.path.join(CSRC, "mk_persist.hip"), os.path.join(CSRC, "mk_mfma_core.h"),
                  os.path.join(CSRC, "mk_ks_core.h")]),
 }
-PERSIST_KERNEL = "persist_rotation_kernel<32>"
+PERSIST_KERNEL = "persist_rotation_kernel<32, 8>"
 
 
 # Stage-1 GEMM instantiation run for each tile shape (the shape table of
