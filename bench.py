@@ -442,6 +442,7 @@ def batch_scaling(torch, mk, ctx, sizes):
         want = np.array([mi.plain_gate(int(x), int(y), int(z)) for x, y, z in zip(types, m1, m2)])
         assert np.array_equal(ctx.decrypt(out.cpu().numpy().view(np.uint32)), want), "batch %d" % n
         res[str(n)] = {"gates_per_s": n / dt, "ms_per_batch": dt * 1e3, "tiles": list(tiles[:2]),
+                       "persistent_team_rows": ctx.get_team_rows(n),
                        "whole_gate_int8_tops": 8 * macs_per_gate(C2) * n / dt / 1e12}
     print("bench: batch sizes measured", file=sys.stderr, flush=True)
     return res
@@ -508,8 +509,8 @@ def main():
                     help="16-bit operators and their operand pairs (config 4; empty: skip); the adder, "
                          "subtractor and multiplier run through HIP graphs, the divider eagerly")
     ap.add_argument("--c5", type=int, default=1, help="run the LR gradient-descent step (config 5; 0: skip)")
-    ap.add_argument("--batch-sizes", default="2048,4096",
-                    help="larger batches of the same gate mix to time (comma list; 0 or empty: skip)")
+    ap.add_argument("--batch-sizes", default="256,512,2048,4096",
+                    help="other batch sizes of the same gate mix to time (comma list; 0 or empty: skip)")
     ap.add_argument("--operator-subbatch", type=int, default=0,
                     help="run the 16-bit multiplier and divider eagerly in sub-batches of this many pairs "
                          "(0: one batch)")

@@ -430,8 +430,10 @@ int mk_set_ks_fusion(mk_ctx *ctx, int on);
  * XCD per tile) when no XCD has more than one tile, 4 (teams of 16) at two
  * tiles per XCD, 8 (teams of 8, the most MFMAs per key tile loaded) from
  * three on.  rows = 2, 4 or 8 forces that size (tuning and tests).  Every
- * size gives the same words.  mk_get_team_rows reports the size a batch of
- * `count` gates runs with (also at other N, where it is fixed).
+ * size gives the same words.  mk_get_team_rows reports the size a rotation
+ * of `count` gates runs with (also at other N, where it is fixed), or 0 when
+ * it runs on the stream-ordered kernels (always before mk_upload_eval_key,
+ * which finds the XCDs).
  * Errors: MK_EINVAL (other values, or rows != 0 at N != 1024). */
 int mk_set_team_rows(mk_ctx *ctx, int rows);
 int mk_get_team_rows(const mk_ctx *ctx, size_t count, int32_t *rows);

@@ -48,6 +48,8 @@ int mfma_upload(mk_ctx *ctx, const std::vector<uint32_t> &evk, hipStream_t s);
 int launch_br_mfma(mk_ctx *ctx, const uint32_t *abar, uint32_t *acc, size_t count, int steps,
                    hipStream_t s, uint32_t *ks_out = nullptr, size_t ks_stride = 0, bool *ks_done = nullptr);
 size_t mfma_scratch_need(const mk_params &P, size_t count);
+// Whether a rotation of GT gate tiles runs on the persistent schedule.
+bool use_persist(const mk_ctx *ctx, int GT);
 // Gates of the first of two consecutive rotation launches for a batch of
 // `count` (count itself when one launch is best).
 size_t mfma_rotation_split(const mk_ctx *ctx, size_t count);

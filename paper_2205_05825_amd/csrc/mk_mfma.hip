@@ -605,7 +605,7 @@ static uint32_t *ctl_of(const MfmaArgs &a) {
 // 92.4 / 79.4 (8), 1024 gates 101.6 / 88.0 (8).  Below one tile per XCD
 // whole XCDs would idle, while the stream-ordered kernels split a tile over
 // many compute units.
-static bool use_persist(const mk_ctx *ctx, int GT) {
+bool use_persist(const mk_ctx *ctx, int GT) {
     const DeviceKeys &D = ctx->dev;
     if (D.rot_kind == MK_ROT_STREAM || D.num_xcd <= 0 || !persist_supported(ctx->p)) return false;
     if (D.rot_kind == MK_ROT_PERSISTENT) return true;

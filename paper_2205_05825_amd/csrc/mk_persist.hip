@@ -641,7 +641,8 @@ int mk_set_team_rows(mk_ctx *ctx, int rows) {
 
 int mk_get_team_rows(const mk_ctx *ctx, size_t count, int32_t *rows) {
     if (!ctx || !rows) return fail(MK_EINVAL, "mk_get_team_rows: null argument");
-    *rows = persist_team_rows(ctx, (int)((count + 31) / 32));
+    const int GT = (int)((count + 31) / 32);
+    *rows = use_persist(ctx, GT) ? persist_team_rows(ctx, GT) : 0;
     return MK_OK;
 }
 

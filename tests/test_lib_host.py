@@ -154,15 +154,14 @@ def test_schedule_switch_arguments():
     big = mk.Context(helpers.lib_params(OP.C2), 3)          # N = 1024: three team sizes
     for rows in (2, 4, 8, 0):
         big.set_team_rows(rows)
-        if rows:
-            assert big.get_team_rows(4096) == rows
+        assert big.get_team_rows(4096) == 0                 # no XCDs probed: stream-ordered
     for bad in (1, 3, 16, -1):
         with pytest.raises(mk.MkError):
             big.set_team_rows(bad)
     with pytest.raises(mk.MkError):                         # fixed size at N = 256
         ctx.set_team_rows(4)
     ctx.set_team_rows(0)
-    assert ctx.get_team_rows(1000) == 4
+    assert ctx.get_team_rows(1000) == 0
 
 
 def test_builder_and_parameter_limits():
