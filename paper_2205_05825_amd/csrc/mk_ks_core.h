@@ -100,7 +100,13 @@ __device__ __forceinline__ void ks_round_unit(const uint32_t *__restrict__ acc, 
     }
     if (i == 0 && q0 == 0 && tid < 32) {
         const size_t g = (size_t)gt * 32 + tid;
-        if (g < count) out[g * stride] = ld(acc + g * K1 * (size_t)N) + 0x20000000u;
+        if (g < count) {
+            const uint32_t b = ld(acc + g * K1 * (size_t)N) + 0x20000000u;
+            // in the same launch the GEMM tasks add to this word with
+            // device-scope atomics, so it is written at that scope too
+            if constexpr (COH) __hip_atomic_store(out + g * stride, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            else out[g * stride] = b;
+        }
     }
     __syncthreads();   // `tile` is reused by the next unit
 }
