@@ -217,3 +217,29 @@ def test_add16_2200_pairs_chunked_levels(torch_cuda):
     assert len(picks) == mk.circuit_stats(circ)[0]
     dec = np.stack([ctx.decrypt(x) for x in outs])
     assert np.array_equal(mi.from_bits(dec.T), _wrap(a + b, 16))
+
+
+@pytest.mark.parametrize("op", ["add"])
+def test_full_circuit_oracle_pairs_table7(torch_cuda, op):
+    """4-bit adder on 256 pairs at the Table 7 shape (levels of 256 gates
+    and more: the persistent rotation with key switching fused, teams sized
+    to each level); three seeded pairs run through the whole circuit in the
+    oracle (about a minute on the host's cores), from the same input
+    ciphertexts, and every output word of those pairs equals the GPU's.  All
+    256 sums decrypt."""
+    import paper_2205_05825_amd as mk
+    from oracle import circuits as C
+    K, ctx = helpers.gpu_world("C2")
+    k, pairs = 4, 256
+    code, build = {"add": (mk.OP_ADD, C.adder), "sub": (mk.OP_SUB, C.subtractor)}[op]
+    circ = mk.build_operator(code, k)
+    a, b = mi.operand_pairs(pairs, k, seed=70 + code)
+    in_ct = np.concatenate([helpers.encrypt_operands(K, a, k, 0, 7000 + code),
+                            helpers.encrypt_operands(K, b, k, 1, 7100 + code)])
+    words, _ = _words(torch_cuda, ctx, circ, in_ct)
+    pick = [0] + sorted(np.random.default_rng(code).choice(np.arange(1, pairs - 1), 1, replace=False).tolist()) + [pairs - 1]
+    ref = helpers.oracle_circuit("C2", build(k), np.ascontiguousarray(in_ct[:, pick]))
+    assert np.array_equal(words[:, pick, :K.params.lwe_words], ref)
+    dec = np.stack([tfhe.decrypt(K, o) for o in words])
+    want = _wrap(a + b, k) if op == "add" else _wrap(a - b, k)
+    assert np.array_equal(mi.from_bits(dec.T), want)
