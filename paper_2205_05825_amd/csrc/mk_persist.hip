@@ -19,7 +19,8 @@
 //       tile hands its finished c'_j to LDS and restarts for c'_{j+1}
 //       without draining the pipeline).  Both halves contract L*ell
 //       polynomials.
-//   S2  ACC_{o ? 1+i : 0} += sum_l T(f_o,l) V_l, one (o, rb) task per member.
+//   S2  ACC_{o ? 1+i : 0} += sum_l T(f_o,l) V_l, one (o, rb) task per member
+//       (the same segmented stream as the c' half, with one segment).
 // This is the hybrid product of the uni-encrypted bootstrapping key (§3.2)
 // with the evaluation key (b_0 = -a, b_1..b_k), in the same order as the
 // stream-ordered kernels, hence bit-identical to them.  When an XCD owns
@@ -214,26 +215,6 @@ __device__ void pass_rotdec(const PersistArgs &p, int u0, int stride, int nunits
     for (int b = u0; b < nunits; b += kMaxRUnits * stride) rotdec_batch(p, b, stride, nunits, step, unit_of, rows);
 }
 
-// Old output rows of the tile (read-modify-write seed), coherent loads; the
-// resource starts at the tile's first gate.
-template <int MR>
-__device__ __forceinline__ void load_old_coherent(__amdgpu_buffer_rsrc_t r, size_t gate_stride, int rb, int lane,
-                                                  v16i (&acc)[MR][1]) {
-    const int g = lane & 31;
-#pragma unroll
-    for (int rr = 0; rr < MR; ++rr) {
-        const uint32_t w0 = (uint32_t)((size_t)g * gate_stride + 32 * (rb * MR + rr) + 4 * (lane / 32));
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const v4i v = ld_coherent(r, (w0 + 8 * q) * 4);
-            acc[rr][0][4 * q + 0] = v[0];
-            acc[rr][0][4 * q + 1] = v[1];
-            acc[rr][0][4 * q + 2] = v[2];
-            acc[rr][0][4 * q + 3] = v[3];
-        }
-    }
-}
-
 // Limb combination in one LDS round: every wave writes all MR of its limb
 // tiles, shifted by 8 t (limb t weighs 2^(8t)), then after one barrier wave
 // t sums quad t (registers 4t..4t+3, i.e. words 8t..8t+3 of its lane's row
@@ -265,18 +246,6 @@ __device__ __forceinline__ void limb_sums(const v16i (&acc)[MR][1], int t, int l
     }
 }
 
-// Row tile i of the task (rows 32 (rb MR + i) ..): the thread's 4 words
-// 8 t + 4 h .. + 3 of its lane's gate go to `base` (gate stride given).
-template <int MR>
-__device__ __forceinline__ void store_sums(uint32_t *base, size_t gate_stride, int tile, int rb, int t, int lane,
-                                           const uint4 (&sum)[MR]) {
-    const int g = tile * 32 + (lane & 31);
-#pragma unroll
-    for (int i = 0; i < MR; ++i)
-        *reinterpret_cast<uint4 *>(base + (size_t)g * gate_stride + 32 * (rb * MR + i) + 8 * t + 4 * (lane >> 5)) =
-            sum[i];
-}
-
 // The ell digits of w into V: a thread's 4 consecutive coefficients
 // 32 kb + 8 t + 4 h .. + 3 of its lane's gate are bytes 8 (t & 1) + 4 h ..
 // + 3 of fragment piece (kb, lane 32 (t >> 1) + g) of each digit plane.
@@ -304,7 +273,9 @@ __device__ __forceinline__ void store_v_digits(const MfmaArgs &a, int tile, int 
 // One contraction task on tile t, row block rb, wave w = key limb: kind 0 =
 // c'_j into ACC_j for every live slot j (one seamless stream of live x ell
 // polynomials, one segment per slot), 1 = w into V, 2 = stage-2 unit o into
-// ACC_{o ? 1+party : 0}.
+// ACC_{o ? 1+party : 0} (a stream of ell polynomials, one segment).  The
+// read-modify-write kinds hand each finished row to LDS and add the old
+// row, prefetched while the row's last products run, when they store it.
 template <int NB, int MR>
 __device__ __forceinline__ void task_gemm(const PersistArgs &p, int kind, int j_or_o, int t, int rb, int party,
                                           int bit, int live, uint4 *red) {
@@ -325,11 +296,21 @@ __device__ __forceinline__ void task_gemm(const PersistArgs &p, int kind, int j_
     v16i acc[MR][1];
 #pragma unroll
     for (int r = 0; r < MR; ++r) acc[r][0] = v16i{};
-    if (kind == 0) {
-        // d_l against U_{j,l} for j < live: polynomial p = j ell + l
-        o.A = a.bk + bkbit * ell * poly_tiles;
-        o.B = a.U + (size_t)t * NB * kTileBytes;
-        o.ell = live * ell;
+    if (kind == 0 || kind == 2) {
+        // kind 0: d_l against U_{j,l} for j < live: polynomial p = j ell + l,
+        // segment j into slot j; kind 2: f_{o,l} against V_l, one segment
+        // into slot 0 (o = 0) or 1 + party (o = 1)
+        const int out_slot = kind == 0 ? 0 : (j_or_o == 0 ? 0 : 1 + party);
+        const int seg_step = kind == 0 ? 1 : 0;
+        if (kind == 0) {
+            o.A = a.bk + bkbit * ell * poly_tiles;
+            o.B = a.U + (size_t)t * NB * kTileBytes;
+            o.ell = live * ell;
+        } else {
+            o.A = a.bk + ((bkbit + 1 + j_or_o) * ell) * poly_tiles;
+            o.B = a.V + (size_t)t * NB * kTileBytes;
+            o.ell = ell;
+        }
         // the tile's gates: lane g's row tile r of slot s starts at word
         // g K1 N + s N + 32 (rb MR + r); wave w owns words 8 w + 4 h .. + 3
         const __amdgpu_buffer_rsrc_t racc = __builtin_amdgcn_make_buffer_rsrc(
@@ -346,7 +327,10 @@ __device__ __forceinline__ void task_gemm(const PersistArgs &p, int kind, int j_
         uint4 *slots = red;
         slide_gemm_seg<MR, NB, Cfg::D, kCoherent, Cfg::PF>(
             o, ell, w, lane, acc,
-            [&](int r, int s) { return ld_coherent(racc, (lane_word + (uint32_t)(s * N + 32 * r)) * 4u); },
+            [&](int r, int s) {
+                const int slot = out_slot + seg_step * s;
+                return ld_coherent(racc, (lane_word + (uint32_t)(slot * N + 32 * r)) * 4u);
+            },
             [&](int r) {
                 if (r == MR - 1) __syncthreads();
                 uint4 *slot = slots + r * (4 * 4 * 64);
@@ -371,36 +355,21 @@ __device__ __forceinline__ void task_gemm(const PersistArgs &p, int kind, int j_
                         v.z += x.z << (8 * l);
                         v.w += x.w << (8 * l);
                     }
-                    *reinterpret_cast<uint4 *>(tile_acc + lane_word + (size_t)s * N + 32 * r) = v;
+                    *reinterpret_cast<uint4 *>(tile_acc + lane_word + (size_t)(out_slot + seg_step * s) * N + 32 * r) = v;
                 }
             });
+        __syncthreads();   // the slots are reused by the next task
         return;
     }
-    uint32_t *base = a.acc;
-    if (kind == 1) {
-        o.A = a.evk;                                   // b_{j,l}, j < live, flattened
-        o.B = a.U + (size_t)t * NB * kTileBytes;       // U_{j,l}, same order
-        o.ell = live * ell;
-    } else {
-        o.A = a.bk + ((bkbit + 1 + j_or_o) * ell) * poly_tiles;
-        o.B = a.V + (size_t)t * NB * kTileBytes;
-        o.ell = ell;
-        base = a.acc + (size_t)(j_or_o == 0 ? 0 : 1 + party) * N;
-    }
-    // the tile's rows of the read-modify-write output (w has none)
-    const __amdgpu_buffer_rsrc_t rbase = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)(base + (size_t)t * 32 * gate_stride), (short)0, (int)(32 * gate_stride * 4), kBufWord3);
-    // the old output values are loaded before the contraction's own loads
-    // and turned into limb seeds (registers only) once those are in flight
-    const bool seed = kind != 1 && (w == 0 || w == 3);
-    if (seed) load_old_coherent<MR>(rbase, gate_stride, rb, lane, acc);
-    slide_gemm<MR, NB, Cfg::D, kCoherent>(o, w, lane, acc, [&]() {
-        if (seed) seed_old<MR, 1>(w, acc);
-    });
+    // kind 1: w = sum over the live slots of b_{j,l} against U_{j,l}, its
+    // limbs combined and decomposed into V
+    o.A = a.evk;                                   // b_{j,l}, j < live, flattened
+    o.B = a.U + (size_t)t * NB * kTileBytes;       // U_{j,l}, same order
+    o.ell = live * ell;
+    slide_gemm<MR, NB, Cfg::D, kCoherent>(o, w, lane, acc, []() {});
     uint4 sum[MR];
     limb_sums<MR>(acc, w, lane, red, sum);
-    if (kind == 1) store_v_digits<MR>(a, t, rb, w, lane, sum);
-    else store_sums<MR>(base, gate_stride, t, rb, w, lane, sum);
+    store_v_digits<MR>(a, t, rb, w, lane, sum);
     __syncthreads();   // red is reused by the next task
 }
 
