@@ -237,6 +237,38 @@ def test_graph_of_a_table7_operator(torch_cuda):
     assert np.array_equal(mi.from_bits(dec.T), _wrap(a + b, k))
 
 
+def test_graph_of_persistent_levels_table7(torch_cuda):
+    """A 4-bit adder on 256 pairs at the Table 7 shape captured as a graph:
+    its levels of 256 gates and more run the persistent rotation (teams of
+    32, 16 or 8 by width) with key switching inside the launch.  Three
+    launches, with an eager evaluation between them, equal the eager words,
+    and the sums decrypt."""
+    import paper_2205_05825_amd as mk
+    K, ctx = helpers.gpu_world("C2")
+    k, batch = 4, 256
+    circ = mk.build_operator(mk.OP_ADD, k)
+    a, b = mi.operand_pairs(batch, k, seed=9)
+    in_ct = np.concatenate([helpers.encrypt_operands(K, a, k, 0, 900),
+                            helpers.encrypt_operands(K, b, k, 1, 910)])
+    d = torch_cuda.device("cuda:0")
+    inp = torch_cuda.from_numpy(np.ascontiguousarray(in_ct).view(np.int32)).to(d)
+    out = torch_cuda.zeros((k, batch, in_ct.shape[2]), dtype=torch_cuda.int32, device=d)
+    g = ctx.circuit_graph(circ, inp, out, path=1)
+    try:
+        eager = _eval(torch_cuda, ctx, circ, in_ct, 1)
+        for _ in range(3):
+            out.fill_(0)
+            g.launch()
+            torch_cuda.cuda.synchronize()
+            ctx.device_status()
+            assert np.array_equal(out.cpu().numpy().view(np.uint32), eager)
+            _eval(torch_cuda, ctx, circ, in_ct, 1)
+    finally:
+        g.close()
+    dec = np.stack([tfhe.decrypt(K, o) for o in eager])
+    assert np.array_equal(mi.from_bits(dec.T), _wrap(a + b, k))
+
+
 @pytest.mark.parametrize("t", range(7))
 def test_naive_gates_parity(torch_cuda, t):
     """NAND-composed gates (Table 2's comparison design) through the engine:
