@@ -50,7 +50,7 @@ CSRC = os.path.join(ROOT, "paper_2205_05825_amd", "csrc")
 # sha256 of those sources matches the one it records.
 TRAFFIC = {
     "gemm1": (os.path.join(ROOT, "profiles", "mfma_gemm1_c2_1024gates_hbm_traffic.md"),
-              [os.path.join(CSRC, "mk_mfma.hip")]),
+              [os.path.join(CSRC, "mk_mfma.hip"), os.path.join(CSRC, "mk_mfma_core.h")]),
     "persist": (os.path.join(ROOT, "profiles", "persist_rotation_c2_1024gates_hbm_traffic.md"),
                 [os.path.join(CSRC, "mk_persist.hip"), os.path.join(CSRC, "mk_mfma_core.h"),
                  os.path.join(CSRC, "mk_ks_core.h")]),
@@ -522,6 +522,8 @@ def main():
                     help="input pairs of the scheme-vs-NAND-composed gate comparison (0: skip)")
     ap.add_argument("--tiles", default="", metavar="G1,G2",
                     help="force the two GEMM tile shapes instead of autotuning")
+    ap.add_argument("--rotation", choices=["auto", "stream", "persistent"], default="auto",
+                    help="schedule of the MFMA rotation for every run of this process (mk_set_rotation)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run one device-to-device copy of MIB MiB (reference "
@@ -554,6 +556,7 @@ def main():
     for i in range(P.k):
         ctx.keygen(i, (SEED + 1 + i) & 0xFFFFFFFFFFFFFFFF)
     ctx.upload()
+    ctx.set_rotation({"auto": mk.ROT_AUTO, "stream": mk.ROT_STREAM, "persistent": mk.ROT_PERSISTENT}[args.rotation])
     types, m1, m2 = mi.gate_batch(BATCH, seed=SEED)
     c1 = ctx.encrypt(0, m1, seed=200)
     c2 = ctx.encrypt(1, m2, seed=201)
