@@ -139,8 +139,10 @@ def cpu_baseline(gates_per_core: int):
     """The oracle, as it stands, on bounded samples of the workloads, one
     process per host core for the all-core rates (fork before any GPU use):
     the C2 gate mix (the headline workload: gates_per_core gates per core
-    on all cores, and one gate on one core) and the 8-gate C1 truth-table
-    workload (all 8 gates on one core and on all cores)."""
+    on all cores, and four gates on one core), the 8-gate C1 truth-table
+    workload (all 8 gates on one core and on all cores), and one 4-party
+    gate per core at the C3 shape (the basis of the config 3
+    extrapolation)."""
     import multiprocessing as mp
 
     from oracle import params as OP
@@ -158,6 +160,11 @@ def cpu_baseline(gates_per_core: int):
     e1, e2 = tfhe.encrypt(K1, 0, a1, seed=0), tfhe.encrypt(K1, 1, b1, seed=1)
     c1_one = _cpu_rate(ctx, K1, t1, a1, b1, e1, e2, list(range(len(t1))), 1)
     c1_all = _cpu_rate(ctx, K1, t1, a1, b1, e1, e2, list(range(len(t1))), min(cores, len(t1)))
+    # one 4-party gate per core (the C3 shape), for the C3 extrapolation
+    K3 = tfhe.generate(OP.C3, 3)
+    t3, p3, q3 = mi.gate_batch(cores, seed=3)
+    d1, d2 = tfhe.encrypt(K3, 0, p3, seed=300), tfhe.encrypt(K3, OP.C3.k - 1, q3, seed=301)
+    c3_all = _cpu_rate(ctx, K3, t3, p3, q3, d1, d2, list(range(cores)), cores)
     return {"value": all_rate, "unit": "gates/s", "cores": cores, "kind": "oracle",
             "sample": "%d of the %d workload gates (%d per core) on %d cores, %.1f s wall, decrypt %s"
                       % (cores * gates_per_core, BATCH, gates_per_core, cores, all_dt, "ok" if all_ok else "FAILED"),
@@ -167,7 +174,10 @@ def cpu_baseline(gates_per_core: int):
                                "all_core_gates_per_s": c1_all[0], "all_core_processes": min(cores, len(t1)),
                                "decrypts_to_truth_table": bool(c1_one[2] and c1_all[2]),
                                "note": "C1 (k=2, n=64, N=256, ell=2, toy noise): 4 XOR + 4 NAND on every "
-                                       "input pair"}}
+                                       "input pair"},
+            "c3_four_party": {"value": c3_all[0], "unit": "gates/s", "cores": cores,
+                              "sample": "%d mixed gates at k=4 (one per core), %.1f s wall, decrypt %s"
+                                        % (cores, c3_all[1], "ok" if c3_all[2] else "FAILED")}}
 
 
 # ---------------------------------------------------------------- GPU ----
@@ -715,7 +725,31 @@ def main():
         res["plain_i32"] = {"value": BATCH / psec, "ms_per_step": psec * 1e3,
                             "blind_rotate_ms": pms[1] / max(pln[1], 1)}
         res["mfma_vs_plain"] = value / (BATCH / psec)
+    if cpu:
+        res["cpu_baseline"]["extrapolated"] = oracle_extrapolation(cpu, res)
     print(json.dumps(res))
+
+
+def oracle_extrapolation(cpu, res):
+    """Seconds the oracle would take on the host cores for the configs 3-5
+    workloads just run on the GPU: their bootstrapped-gate counts over the
+    oracle's measured all-core rate (the 4-party sample for config 3, the
+    2-party C2 sample otherwise).  An extrapolation, not a measurement."""
+    out = {"basis": "gate count / measured all-core oracle rate on %d cores; not run" % cpu["cores"]}
+    rate2, rate4 = cpu["value"], cpu["c3_four_party"]["value"]
+    jobs = []
+    c3 = res.get("c3_multiplier8_4party")
+    if c3:
+        jobs.append(("c3_mul8", c3["gates_per_pair"] * c3["pairs"], rate4, c3["seconds"]))
+    for op, r in res.get("c4_operators_16bit", {}).items():
+        jobs.append(("c4_%s16" % op, r["gates_per_pair"] * r["pairs"], rate2, r["seconds"]))
+    c5 = res.get("c5_lr_step")
+    if c5:
+        jobs.append(("c5_lr_step", c5["gates"], rate2, c5["seconds"]))
+    for name, gates, rate, gpu_s in jobs:
+        out[name] = {"gates": gates, "oracle_s": gates / rate, "gpu_s": gpu_s,
+                     "gpu_speedup": gates / rate / gpu_s}
+    return out
 
 
 if __name__ == "__main__":
